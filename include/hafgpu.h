@@ -1,0 +1,188 @@
+/*
+ * hafgpu -- hafnians and loop hafnians of complex symmetric matrices on AMD
+ * Instinct MI355X (gfx950), behind a plain C ABI.
+ *
+ * Method: the inclusion-exclusion formula over the 2^(n/2) subsets Z of the
+ * vertex pairs (2i, 2i+1) (Sec. 3.2, Eq. Pset), each term
+ *     f(Z) = [lambda^(n/2)] exp( sum_k ( tr(B^k) / (2k) [+ l_k / 2] ) lambda^k )
+ * with B the submatrix of X*A on the rows/columns of Z (Eq. matA, Eq. poly,
+ * Eq. haffinal; X swaps the two vertices of each pair) and, for the loop
+ * hafnian, the loop moments l_k = d^T B^(k-1) X d of the diagonal d (the loop
+ * formula of Sec. 3.3, read as the walk count of Sec. 3.1).  The power traces
+ * come from a Hessenberg reduction and the characteristic polynomial
+ * (App. B).  Every step runs in complex double on the GPU; the signed outer
+ * sum is accumulated in double-double.
+ *
+ * Data layout: a matrix is row-major interleaved complex128 (haf_cplx,
+ * byte-compatible with numpy / torch complex128), element (i, j) at
+ * A[i * lda + j], lda >= n.
+ *
+ * Errors: every entry point returns an int status (HAF_OK = 0 or a HAF_E_*
+ * code) and never throws; haf_last_error() gives a thread-local message.
+ *
+ * Streams are passed as void* and are hipStream_t values (NULL = the null
+ * stream).  Entry points named *_dev take device pointers, enqueue work on the
+ * stream and return without waiting; the caller keeps inputs and outputs alive
+ * until the stream passes the call.  Host entry points (no _dev suffix) copy in,
+ * run and copy out synchronously, and keep nothing after returning.
+ */
+#ifndef HAFGPU_H
+#define HAFGPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } haf_cplx;
+/* a complex value as unevaluated sums re_hi + re_lo, im_hi + im_lo (double-double) */
+typedef struct { double re_hi, re_lo, im_hi, im_lo; } haf_cplx2;
+
+enum {
+    HAF_OK = 0,
+    HAF_E_INVALID_ARG = 1,   /* null pointer, n < 0, lda < n, unknown kind, count < 0 */
+    HAF_E_TOO_LARGE = 2,     /* n > HAF_MAX_N (after padding an odd n for lhaf)      */
+    HAF_E_NOT_SYMMETRIC = 3, /* A[i][j] != A[j][i] exactly (the method assumes A = A^T, Sec. 2) */
+    HAF_E_NONFINITE = 4,     /* NaN or Inf entry                                      */
+    HAF_E_DEVICE = 5,        /* a HIP call failed                                     */
+    HAF_E_NOMEM = 6,         /* device or host allocation failed                      */
+    HAF_E_BUSY = 7,          /* serving: no free request slot and the queue is full  */
+    HAF_E_STATE = 8          /* serving: unknown ticket / server stopped              */
+};
+
+#define HAF_MAX_N 64         /* subset masks are 32-bit and a subset matrix fits one 64-lane wave */
+#define HAF_KIND_HAF 0
+#define HAF_KIND_LHAF 1
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* haf_last_error(void);
+
+/* Library version string. */
+const char* haf_version(void);
+
+/* Select and initialise a HIP device for this thread's subsequent calls
+ * (optional: the current device is initialised lazily). */
+int haf_init(int device);
+
+/* One-line description of the device and kernel configuration into buf. */
+int haf_device_info(char* buf, int buflen);
+
+/*
+ * haf(A) (Sec. 2, Eq. hafA), host pointers, synchronous.  The diagonal of A is
+ * ignored.  n = 0 gives 1, odd n gives 0.  A must be exactly symmetric and
+ * finite.  n <= 64.
+ */
+int haf_c128(const haf_cplx* A, int n, int lda, haf_cplx* out);
+
+/*
+ * lhaf(A) (the loop hafnian of Sec. 2; diagonal entries are loop weights),
+ * host pointers, synchronous.  Odd n is computed as lhaf(A (+) [1]) (an
+ * isolated vertex whose loop has weight 1).  n <= 63 for odd n, 64 for even.
+ */
+int lhaf_c128(const haf_cplx* A, int n, int lda, haf_cplx* out);
+
+/* Either kind (HAF_KIND_HAF / HAF_KIND_LHAF), result as double-double. */
+int haf_c128x2_host(const haf_cplx* A, int n, int lda, int kind, haf_cplx2* out);
+
+/*
+ * Device variants: dA is a device matrix, d_out a device haf_cplx (or
+ * haf_cplx2 for the x2 form).  Only n, lda and the pointers are checked; the
+ * matrix contents are not inspected (they are on the device), so the caller
+ * guarantees symmetry.  Scratch memory comes from a library-owned pool kept per
+ * (device, stream); it is allocated or grown on first use and kept until
+ * haf_release_workspaces().
+ */
+int haf_c128_dev(const haf_cplx* dA, int n, int lda, haf_cplx* d_out, void* stream);
+int lhaf_c128_dev(const haf_cplx* dA, int n, int lda, haf_cplx* d_out, void* stream);
+int haf_c128x2_dev(const haf_cplx* dA, int n, int lda, int kind, haf_cplx2* d_out, void* stream);
+
+/*
+ * The unsigned terms f(Z) (Sec. 3.3, Eq. haffinal without the outer sum) for
+ * the subsets given as bit masks over the n/2 pairs (bit i = pair (2i, 2i+1)).
+ * d_masks: device uint32[count]; d_terms: device haf_cplx[count].  Exposes the
+ * per-subset stage for sampled checks at sizes where the full sum is out of
+ * reach of a CPU reference.  n even, 2 <= n <= 64, masks nonzero and < 2^(n/2).
+ */
+int haf_terms_dev(const haf_cplx* dA, int n, int lda, int kind, const uint32_t* d_masks, int count,
+                  haf_cplx* d_terms, void* stream);
+
+/*
+ * Batched: count independent hafnians / loop hafnians of uneven sizes in one
+ * persistent launch (plus one reduction launch).  Matrix t is stored densely
+ * (lda = n_t) at element offset h_offsets[t] of dA_packed (device).  h_n,
+ * h_offsets and h_kind are host arrays (the planner runs on the host); d_out is
+ * a device haf_cplx[count].  Each result is bitwise identical to the plain
+ * path's result for the same matrix.
+ */
+int haf_batched_c128(const haf_cplx* dA_packed, const int64_t* h_offsets, const int32_t* h_n,
+                     const uint8_t* h_kind, int count, haf_cplx* d_out, void* stream);
+
+/* Free every cached workspace of every device (waits for the device first). */
+int haf_release_workspaces(void);
+
+/* Kernel path selection (for testing): 0 = automatic, 1 = LDS kernel only,
+ * 2 = register-tiled kernel wherever its size range allows.  Process-wide. */
+int haf_set_kernel_path(int path);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing.  While enabled, every coefficient launch (the per-subset
+ * Hessenberg / characteristic-polynomial stage) and every series launch is
+ * bracketed by HIP events recorded on the launch's own stream.               */
+typedef struct {
+    int64_t coef_launches;      /* coefficient kernel launches                         */
+    double coef_ms;             /* summed event time of those launches                 */
+    double coef_model_flops;    /* model flops of the subsets they processed:
+                                   (44/3) s^3 per subset, + 8 (N-1) s^2 for loop hafnians */
+    int64_t coef_subsets;       /* subsets they processed                              */
+    int64_t series_launches;
+    double series_ms;
+} haf_profile;
+
+/* Start (on != 0) or stop recording; starting clears earlier records. */
+int haf_profile_enable(int on);
+/* Wait for the recorded launches and sum their times into *out. */
+int haf_profile_read(haf_profile* out);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: a continuous-batching request server.                            */
+typedef struct haf_server haf_server;
+
+typedef struct {
+    int device;                 /* HIP device ordinal                                  */
+    int64_t arena_bytes;        /* device bytes for admitted requests (matrices + state) */
+    int max_active;             /* request slots on the device                          */
+    int max_queue;              /* host queue length before submit returns HAF_E_BUSY   */
+    int tick_units;             /* work units (subset chunks) launched per step         */
+    int continuous;             /* 1: admit between steps (continuous batching);
+                                   0: one request at a time, FIFO (the plain server)    */
+} haf_server_config;
+
+typedef struct {
+    uint64_t ticket;
+    int status;                 /* HAF_OK or an error code                              */
+    int n, kind;
+    haf_cplx value;
+    double t_submit, t_admit, t_done;   /* seconds on the host steady clock           */
+} haf_result;
+
+/* Fill *cfg with defaults. */
+void haf_server_default_config(haf_server_config* cfg);
+/* Start a server (its scheduler thread owns one HIP stream). NULL on failure. */
+haf_server* haf_server_create(const haf_server_config* cfg);
+/* Copy the host matrix A and queue it; non-blocking.  *ticket identifies it. */
+int haf_server_submit(haf_server* s, const haf_cplx* A, int n, int lda, int kind, uint64_t* ticket);
+/* Move up to max finished results into out; *n_out tells how many. */
+int haf_server_poll(haf_server* s, haf_result* out, int max, int* n_out);
+/* Block until every submitted request has finished. */
+int haf_server_drain(haf_server* s);
+/* Stop the scheduler and free its device memory (pending requests fail). */
+void haf_server_destroy(haf_server* s);
+/* Seconds on the steady clock used for the t_* fields. */
+double haf_now(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HAFGPU_H */

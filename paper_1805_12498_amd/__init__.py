@@ -1,0 +1,18 @@
+"""hafgpu: hafnians and loop hafnians on MI355X (gfx950) through a C-ABI HIP library.
+
+The Python layer only marshals arguments; see ``_native`` and ``include/hafgpu.h``.
+"""
+from ._native import (  # noqa: F401
+    KIND_HAF, KIND_LHAF, HafError, Server, batched_dev, device_info, haf_dev, haf_host, load, now,
+    profile_enable, profile_read, release_workspaces, set_kernel_path, terms_dev,
+)
+
+
+def haf(A):
+    """haf(A) of a host matrix (numpy-compatible), computed on the GPU."""
+    return haf_host(A, KIND_HAF)
+
+
+def lhaf(A):
+    """lhaf(A) of a host matrix, computed on the GPU."""
+    return haf_host(A, KIND_LHAF)

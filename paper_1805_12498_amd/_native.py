@@ -1,0 +1,241 @@
+"""ctypes binding of libhafgpu.so: argument marshalling only.
+
+Every computation runs in the HIP library; if the library is missing this
+module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhafgpu.so")
+
+HAF_OK = 0
+KIND_HAF = 0
+KIND_LHAF = 1
+ERRORS = {
+    1: "HAF_E_INVALID_ARG", 2: "HAF_E_TOO_LARGE", 3: "HAF_E_NOT_SYMMETRIC", 4: "HAF_E_NONFINITE",
+    5: "HAF_E_DEVICE", 6: "HAF_E_NOMEM", 7: "HAF_E_BUSY", 8: "HAF_E_STATE",
+}
+
+# every symbol declared in include/hafgpu.h
+EXPORTS = (
+    "haf_last_error", "haf_version", "haf_init", "haf_device_info", "haf_c128", "lhaf_c128", "haf_c128x2_host",
+    "haf_c128_dev", "lhaf_c128_dev", "haf_c128x2_dev", "haf_terms_dev", "haf_batched_c128",
+    "haf_release_workspaces", "haf_set_kernel_path", "haf_server_default_config", "haf_server_create",
+    "haf_server_submit", "haf_server_poll", "haf_server_drain", "haf_server_destroy", "haf_now",
+    "haf_profile_enable", "haf_profile_read",
+)
+
+
+class HafError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (ERRORS.get(code, str(code)), msg))
+        self.code = code
+
+
+class c128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class c128x2(ctypes.Structure):
+    _fields_ = [("re_hi", ctypes.c_double), ("re_lo", ctypes.c_double), ("im_hi", ctypes.c_double),
+                ("im_lo", ctypes.c_double)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("arena_bytes", ctypes.c_int64), ("max_active", ctypes.c_int),
+                ("max_queue", ctypes.c_int), ("tick_units", ctypes.c_int), ("continuous", ctypes.c_int)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("coef_launches", ctypes.c_int64), ("coef_ms", ctypes.c_double), ("coef_model_flops", ctypes.c_double),
+                ("coef_subsets", ctypes.c_int64), ("series_launches", ctypes.c_int64), ("series_ms", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int), ("n", ctypes.c_int), ("kind", ctypes.c_int),
+                ("value", c128), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError("libhafgpu.so not built: run `python -m paper_1805_12498_amd.build`")
+    # PyTorch ships its own HIP runtime under the same soname.  Loading torch first
+    # makes the library bind to that one, so device pointers and streams coming
+    # from torch belong to the runtime the library uses (one runtime per process).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    vp, i, i64, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+    sig = {
+        "haf_last_error": ([], ctypes.c_char_p),
+        "haf_version": ([], ctypes.c_char_p),
+        "haf_init": ([i], i),
+        "haf_device_info": ([ctypes.c_char_p, i], i),
+        "haf_c128": ([vp, i, i, vp], i),
+        "lhaf_c128": ([vp, i, i, vp], i),
+        "haf_c128x2_host": ([vp, i, i, i, vp], i),
+        "haf_c128_dev": ([vp, i, i, vp, vp], i),
+        "lhaf_c128_dev": ([vp, i, i, vp, vp], i),
+        "haf_c128x2_dev": ([vp, i, i, i, vp, vp], i),
+        "haf_terms_dev": ([vp, i, i, i, vp, i, vp, vp], i),
+        "haf_batched_c128": ([vp, vp, vp, vp, i, vp, vp], i),
+        "haf_release_workspaces": ([], i),
+        "haf_set_kernel_path": ([i], i),
+        "haf_server_default_config": ([vp], None),
+        "haf_server_create": ([vp], vp),
+        "haf_server_submit": ([vp, vp, i, i, i, ctypes.POINTER(u64)], i),
+        "haf_server_poll": ([vp, vp, i, ctypes.POINTER(i)], i),
+        "haf_server_drain": ([vp], i),
+        "haf_server_destroy": ([vp], None),
+        "haf_now": ([], ctypes.c_double),
+        "haf_profile_enable": ([i], i),
+        "haf_profile_read": ([vp], i),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _ = i64
+    _lib = lib
+    return lib
+
+
+def check(rc: int):
+    if rc != HAF_OK:
+        raise HafError(rc, load().haf_last_error().decode())
+
+
+def _host_matrix(A):
+    A = np.asarray(A)
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("expected a square matrix")
+    return np.ascontiguousarray(A, dtype=np.complex128)
+
+
+def haf_host(A, kind: int = KIND_HAF, x2: bool = False):
+    """haf / lhaf of a host matrix (synchronous).  x2 returns (re_hi, re_lo, im_hi, im_lo)."""
+    A = _host_matrix(A)
+    n = A.shape[0]
+    lib = load()
+    ptr = A.ctypes.data if n else ctypes.addressof(ctypes.c_double(0.0))
+    if x2:
+        out = c128x2()
+        check(lib.haf_c128x2_host(ctypes.c_void_p(ptr), n, max(n, 1), kind, ctypes.byref(out)))
+        return (out.re_hi, out.re_lo, out.im_hi, out.im_lo)
+    out = c128()
+    fn = lib.haf_c128 if kind == KIND_HAF else lib.lhaf_c128
+    check(fn(ctypes.c_void_p(ptr), n, max(n, 1), ctypes.byref(out)))
+    return complex(out.re, out.im)
+
+
+def haf_dev(dA_ptr: int, n: int, lda: int, d_out_ptr: int, stream: int = 0, kind: int = KIND_HAF, x2: bool = False):
+    """Enqueue haf / lhaf of a device matrix; raw device pointers and a hipStream_t value."""
+    lib = load()
+    if x2:
+        rc = lib.haf_c128x2_dev(ctypes.c_void_p(dA_ptr), n, lda, kind, ctypes.c_void_p(d_out_ptr),
+                                ctypes.c_void_p(stream))
+    else:
+        fn = lib.haf_c128_dev if kind == KIND_HAF else lib.lhaf_c128_dev
+        rc = fn(ctypes.c_void_p(dA_ptr), n, lda, ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(stream))
+    check(rc)
+
+
+def terms_dev(dA_ptr: int, n: int, lda: int, kind: int, d_masks_ptr: int, count: int, d_terms_ptr: int,
+              stream: int = 0):
+    check(load().haf_terms_dev(ctypes.c_void_p(dA_ptr), n, lda, kind, ctypes.c_void_p(d_masks_ptr), count,
+                               ctypes.c_void_p(d_terms_ptr), ctypes.c_void_p(stream)))
+
+
+def batched_dev(dA_ptr: int, offsets: np.ndarray, sizes: np.ndarray, kinds: np.ndarray, d_out_ptr: int,
+                stream: int = 0):
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+    kinds = np.ascontiguousarray(kinds, dtype=np.uint8)
+    check(load().haf_batched_c128(ctypes.c_void_p(dA_ptr), ctypes.c_void_p(offsets.ctypes.data),
+                                  ctypes.c_void_p(sizes.ctypes.data), ctypes.c_void_p(kinds.ctypes.data),
+                                  len(sizes), ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(stream)))
+
+
+def set_kernel_path(path: int):
+    check(load().haf_set_kernel_path(path))
+
+
+def device_info() -> str:
+    buf = ctypes.create_string_buffer(512)
+    check(load().haf_device_info(buf, 512))
+    return buf.value.decode()
+
+
+def release_workspaces():
+    check(load().haf_release_workspaces())
+
+
+def profile_enable(on: bool = True):
+    check(load().haf_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    p = Profile()
+    check(load().haf_profile_read(ctypes.byref(p)))
+    return {f: getattr(p, f) for f, _ in Profile._fields_}
+
+
+def now() -> float:
+    return load().haf_now()
+
+
+class Server:
+    """Continuous-batching request server (see include/hafgpu.h)."""
+
+    def __init__(self, **cfg):
+        lib = load()
+        c = ServerConfig()
+        lib.haf_server_default_config(ctypes.byref(c))
+        for k, v in cfg.items():
+            setattr(c, k, v)
+        self._lib = lib
+        self._h = lib.haf_server_create(ctypes.byref(c))
+        if not self._h:
+            raise HafError(8, lib.haf_last_error().decode())
+
+    def submit(self, A, kind: int = KIND_HAF) -> int:
+        A = _host_matrix(A)
+        t = ctypes.c_uint64(0)
+        check(self._lib.haf_server_submit(self._h, ctypes.c_void_p(A.ctypes.data), A.shape[0], A.shape[0], kind,
+                                          ctypes.byref(t)))
+        return t.value
+
+    def poll(self, max_results: int = 1024):
+        buf = (Result * max_results)()
+        got = ctypes.c_int(0)
+        check(self._lib.haf_server_poll(self._h, buf, max_results, ctypes.byref(got)))
+        return [buf[k] for k in range(got.value)]
+
+    def drain(self):
+        check(self._lib.haf_server_drain(self._h))
+
+    def close(self):
+        if self._h:
+            self._lib.haf_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,131 @@
+// Shared device helpers for the hafnian kernels: complex double arithmetic,
+// wave-level primitives and the subset enumeration.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hafgpu {
+
+constexpr int kMaxN = 64;          // matrix size limit
+constexpr int kMaxPairs = 32;      // n / 2
+
+// ---------------------------------------------------------------- complex double
+__device__ __forceinline__ double2 cz() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ double2 cone() { return make_double2(1.0, 0.0); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// acc += a * b
+__device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+}
+// acc -= a * b
+__device__ __forceinline__ void cfms(double2& acc, double2 a, double2 b) {
+    acc.x = fma(-a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(-a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+}
+// acc += conj(a) * b
+__device__ __forceinline__ void cfma_cj(double2& acc, double2 a, double2 b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+}
+// acc -= a * conj(b)
+__device__ __forceinline__ void cfms_cj(double2& acc, double2 a, double2 b) {
+    acc.x = fma(-a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+}
+__device__ __forceinline__ double2 crecip(double2 z) {
+    double d = 1.0 / fma(z.x, z.x, z.y * z.y);
+    return make_double2(z.x * d, -z.y * d);
+}
+
+// ---------------------------------------------------------------- wave primitives
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double2 readlane_c(double2 z, int lane) {
+    return make_double2(readlane_d(z.x, lane), readlane_d(z.y, lane));
+}
+// Butterfly all-reduce over the 64 lanes: every lane adds the same two operands
+// at every stage, so all lanes end with bitwise the same sum.
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+// Columns whose largest entry is below this are treated as already reduced.
+constexpr double kTinyColumn = 0x1p-960;
+
+// ---------------------------------------------------------------- double-double
+struct dd { double hi, lo; };
+__device__ __forceinline__ dd dd_two_sum(double a, double b) {
+    double s = a + b, bb = s - a;
+    return dd{ s, (a - (s - bb)) + (b - bb) };
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+    dd s = dd_two_sum(a.hi, b.hi), t = dd_two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    double h = s.hi + s.lo;
+    s.lo = s.lo - (h - s.hi);
+    s.hi = h;
+    s.lo += t.lo;
+    h = s.hi + s.lo;
+    return dd{ h, s.lo - (h - s.hi) };
+}
+
+// ---------------------------------------------------------------- subsets
+// The rank-th m-subset of {0..N-1} in the combinatorial number system:
+// rank = sum_i C(c_i, i) over the chosen elements c_m > ... > c_1 >= 0,
+// taken greedily from the largest element.  C(c, k) is carried along with
+// C(c-1, k) = C(c, k) (c-k)/c and C(c-1, k-1) = C(c, k) k/c (exact in 64 bits
+// for c <= 32).
+__device__ __forceinline__ uint32_t unrank_subset(uint64_t rank, int m, int N) {
+    uint64_t b = 1;                                   // C(N-1, m)
+    if (m > N - 1) b = 0;
+    else
+        for (int i = 1; i <= m; ++i) b = b * (uint64_t)(N - m - 1 + i) / (uint64_t)i;
+    uint32_t mask = 0;
+    int k = m;
+    for (int c = N - 1; c >= 0 && k > 0; --c) {
+        if (rank >= b) {
+            mask |= 1u << c;
+            rank -= b;
+            b = c > 0 ? b * (uint64_t)k / (uint64_t)c : 0;
+            --k;
+        } else {
+            b = c > 0 ? b * (uint64_t)(c - k) / (uint64_t)c : 0;
+        }
+    }
+    return mask;
+}
+
+// Vertex of row r of the subset matrix: the (r/2)-th chosen pair, member r&1.
+__device__ __forceinline__ int subset_vertex(uint32_t mask, int r) {
+    uint32_t mm = mask;
+    for (int t = 0; t < (r >> 1); ++t) mm &= mm - 1;
+    return 2 * __builtin_ctz(mm) + (r & 1);
+}
+
+}  // namespace hafgpu

@@ -1,0 +1,200 @@
+// Per-subset series and the signed compensated outer sum.
+//
+// Input: for each subset of one size class, the coefficients a_k of
+// det(I - lambda B) (k = 1..N) and, for the loop hafnian, the loop moments l_k.
+// Each thread owns one subset:
+//   power traces   p_k = tr(B^k) = -k a_k - sum_{i<k} a_i p_{k-i}   (Newton's
+//                  identities; App. B's route from the polynomial to the traces),
+//   series         c_k = p_k / (2k) [+ l_k / 2],  f(Z) = [lambda^N] exp(sum_k c_k lambda^k)
+//                  = e_N with e_0 = 1, e_j = (1/j) sum_{k=1}^{j} k c_k e_{j-k}
+//                  (Eq. poly / Eq. haffinal: (1/N!) d^N/dlambda^N of the exponential
+//                  series is its lambda^N coefficient),
+//   signed sum     (-1)^(N-|Z|) f(Z) (Eq. Pset), accumulated in double-double by a
+//                  fixed-shape tree in the block; one partial per block.
+// N is a template parameter so the coefficient arrays stay in registers.
+#include "haf_common.hpp"
+#include "haf_launch.hpp"
+
+namespace hafgpu {
+
+constexpr int kSeriesBlock = 256;
+
+template <int N, bool LOOPS>
+__device__ __forceinline__ double2 subset_series(const double2* __restrict__ coef, int64_t cstride, int t) {
+    double2 a[N + 1], p[N + 1];
+#pragma unroll
+    for (int k = 1; k <= N; ++k) a[k] = coef[(int64_t)(k - 1) * cstride + t];
+    // Newton's identities
+#pragma unroll
+    for (int k = 1; k <= N; ++k) {
+        double2 acc = cscale(a[k], -(double)k);
+#pragma unroll
+        for (int i = 1; i < k; ++i) cfms(acc, a[i], p[k - i]);
+        p[k] = acc;
+    }
+    // k c_k = p_k / 2 [+ k l_k / 2]; kept in p
+#pragma unroll
+    for (int k = 1; k <= N; ++k) {
+        double2 kc = cscale(p[k], 0.5);
+        if (LOOPS) {
+            double2 l = coef[(int64_t)(N + k - 1) * cstride + t];
+            kc.x = fma(0.5 * (double)k, l.x, kc.x);
+            kc.y = fma(0.5 * (double)k, l.y, kc.y);
+        }
+        p[k] = kc;
+    }
+    // exponential series, e_j in place of a_j (a is no longer needed)
+    a[0] = cone();
+#pragma unroll
+    for (int j = 1; j <= N; ++j) {
+        double2 acc = cz();
+#pragma unroll
+        for (int k = 1; k <= j; ++k) cfma(acc, p[k], a[j - k]);
+        a[j] = cscale(acc, 1.0 / (double)j);
+    }
+    return a[N];
+}
+
+// One block = kSeriesBlock subsets.  If terms != nullptr the unsigned f(Z) are
+// written out (no sum); otherwise the block's signed double-double partial goes
+// to partials[4 * (slot0 + blockIdx.x) + {re_hi, re_lo, im_hi, im_lo}].
+template <int N, bool LOOPS>
+__global__ __launch_bounds__(kSeriesBlock) void k_series(const double2* __restrict__ coef, int64_t cstride,
+                                                         int count, double sign, double* __restrict__ partials,
+                                                         int64_t slot0, double2* __restrict__ terms) {
+    const int t = blockIdx.x * kSeriesBlock + threadIdx.x;
+    double2 f = cz();
+    if (t < count) f = subset_series<N, LOOPS>(coef, cstride, t);
+    if (terms) {
+        if (t < count) terms[t] = f;
+        return;
+    }
+    __shared__ double sh[4][kSeriesBlock];
+    const int tid = threadIdx.x;
+    sh[0][tid] = sign * f.x;
+    sh[1][tid] = 0.0;
+    sh[2][tid] = sign * f.y;
+    sh[3][tid] = 0.0;
+    __syncthreads();
+    for (int st = kSeriesBlock / 2; st > 0; st >>= 1) {
+        if (tid < st) {
+            dd r = dd_add(dd{ sh[0][tid], sh[1][tid] }, dd{ sh[0][tid + st], sh[1][tid + st] });
+            dd i = dd_add(dd{ sh[2][tid], sh[3][tid] }, dd{ sh[2][tid + st], sh[3][tid + st] });
+            sh[0][tid] = r.hi; sh[1][tid] = r.lo; sh[2][tid] = i.hi; sh[3][tid] = i.lo;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double* o = partials + 4 * (slot0 + blockIdx.x);
+        o[0] = sh[0][0]; o[1] = sh[1][0]; o[2] = sh[2][0]; o[3] = sh[3][0];
+    }
+}
+
+#define HAF_INST_SERIES(NN)                                                                                    \
+    template __global__ void k_series<NN, false>(const double2*, int64_t, int, double, double*, int64_t, double2*); \
+    template __global__ void k_series<NN, true>(const double2*, int64_t, int, double, double*, int64_t, double2*);
+HAF_INST_SERIES(1) HAF_INST_SERIES(2) HAF_INST_SERIES(3) HAF_INST_SERIES(4)
+HAF_INST_SERIES(5) HAF_INST_SERIES(6) HAF_INST_SERIES(7) HAF_INST_SERIES(8)
+HAF_INST_SERIES(9) HAF_INST_SERIES(10) HAF_INST_SERIES(11) HAF_INST_SERIES(12)
+HAF_INST_SERIES(13) HAF_INST_SERIES(14) HAF_INST_SERIES(15) HAF_INST_SERIES(16)
+HAF_INST_SERIES(17) HAF_INST_SERIES(18) HAF_INST_SERIES(19) HAF_INST_SERIES(20)
+HAF_INST_SERIES(21) HAF_INST_SERIES(22) HAF_INST_SERIES(23) HAF_INST_SERIES(24)
+HAF_INST_SERIES(25) HAF_INST_SERIES(26) HAF_INST_SERIES(27) HAF_INST_SERIES(28)
+HAF_INST_SERIES(29) HAF_INST_SERIES(30) HAF_INST_SERIES(31) HAF_INST_SERIES(32)
+
+// Fixed-order double-double sum of nslots partials (one block of 256 threads):
+// thread t folds slots t, t+256, ... in order, then a fixed tree.  Writes the
+// double-double result (if out_dd) and its rounding to complex double (if out).
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partials, int64_t nslots,
+                                                          double* __restrict__ out_dd, double2* __restrict__ out) {
+    __shared__ double sh[4][256];
+    const int tid = threadIdx.x;
+    dd r{ 0.0, 0.0 }, i{ 0.0, 0.0 };
+    for (int64_t k = tid; k < nslots; k += 256) {
+        const double* p = partials + 4 * k;
+        r = dd_add(r, dd{ p[0], p[1] });
+        i = dd_add(i, dd{ p[2], p[3] });
+    }
+    sh[0][tid] = r.hi; sh[1][tid] = r.lo; sh[2][tid] = i.hi; sh[3][tid] = i.lo;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) {
+            dd a = dd_add(dd{ sh[0][tid], sh[1][tid] }, dd{ sh[0][tid + st], sh[1][tid + st] });
+            dd b = dd_add(dd{ sh[2][tid], sh[3][tid] }, dd{ sh[2][tid + st], sh[3][tid + st] });
+            sh[0][tid] = a.hi; sh[1][tid] = a.lo; sh[2][tid] = b.hi; sh[3][tid] = b.lo;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (out_dd) { out_dd[0] = sh[0][0]; out_dd[1] = sh[1][0]; out_dd[2] = sh[2][0]; out_dd[3] = sh[3][0]; }
+        if (out) *out = make_double2(sh[0][0] + sh[1][0], sh[2][0] + sh[3][0]);
+    }
+}
+
+// Write a constant result (n = 0 gives 1, odd n gives 0 for haf).
+__global__ void k_write_const(double re, double* __restrict__ out_dd, double2* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        if (out_dd) { out_dd[0] = re; out_dd[1] = 0.0; out_dd[2] = 0.0; out_dd[3] = 0.0; }
+        if (out) *out = make_double2(re, 0.0);
+    }
+}
+
+// Copy an n x n matrix (leading dimension lda) into an (n+1) x (n+1) dense one
+// with an isolated vertex whose loop weight is 1 (odd-n loop hafnian).
+__global__ void k_pad_odd(const double2* __restrict__ A, int n, int lda, double2* __restrict__ out) {
+    const int np = n + 1;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < np * np; e += gridDim.x * blockDim.x) {
+        const int i = e / np, j = e % np;
+        double2 v = cz();
+        if (i < n && j < n) v = A[(int64_t)i * lda + j];
+        else if (i == n && j == n) v = cone();
+        out[e] = v;
+    }
+}
+
+}  // namespace hafgpu
+
+namespace hafgpu {
+
+int series_block() { return kSeriesBlock; }
+
+typedef void (*series_fn)(const double2*, int64_t, int, double, double*, int64_t, double2*);
+
+#define HAF_SFN(NN) { k_series<NN, false>, k_series<NN, true> },
+static const series_fn g_series[33][2] = {
+    { nullptr, nullptr },
+    HAF_SFN(1) HAF_SFN(2) HAF_SFN(3) HAF_SFN(4) HAF_SFN(5) HAF_SFN(6) HAF_SFN(7) HAF_SFN(8)
+    HAF_SFN(9) HAF_SFN(10) HAF_SFN(11) HAF_SFN(12) HAF_SFN(13) HAF_SFN(14) HAF_SFN(15) HAF_SFN(16)
+    HAF_SFN(17) HAF_SFN(18) HAF_SFN(19) HAF_SFN(20) HAF_SFN(21) HAF_SFN(22) HAF_SFN(23) HAF_SFN(24)
+    HAF_SFN(25) HAF_SFN(26) HAF_SFN(27) HAF_SFN(28) HAF_SFN(29) HAF_SFN(30) HAF_SFN(31) HAF_SFN(32)
+};
+#undef HAF_SFN
+
+hipError_t launch_series(int N, bool loops, int count, hipStream_t st, const double2* coef, int64_t cstride,
+                         double sign, double* partials, int64_t slot0, double2* terms) {
+    if (N < 1 || N > 32) return hipErrorInvalidValue;
+    if (count <= 0) return hipSuccess;
+    const int blocks = (count + kSeriesBlock - 1) / kSeriesBlock;
+    hipLaunchKernelGGL(g_series[N][loops ? 1 : 0], dim3(blocks), dim3(kSeriesBlock), 0, st, coef, cstride, count,
+                       sign, partials, slot0, terms);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(hipStream_t st, const double* partials, int64_t nslots, double* out_dd, double2* out) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partials, nslots, out_dd, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_write_const(hipStream_t st, double re, double* out_dd, double2* out) {
+    hipLaunchKernelGGL(k_write_const, dim3(1), dim3(64), 0, st, re, out_dd, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_odd(hipStream_t st, const double2* A, int n, int lda, double2* out) {
+    const int np = n + 1;
+    const int blocks = (np * np + 255) / 256;
+    hipLaunchKernelGGL(k_pad_odd, dim3(blocks), dim3(256), 0, st, A, n, lda, out);
+    return hipGetLastError();
+}
+
+}  // namespace hafgpu

@@ -1,0 +1,255 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Tolerance for a full sum (Sec. 3.2): the 2^(n/2)-term alternating sum cancels,
+and each term carries a relative error of a few eps from the complex-double
+Hessenberg / characteristic-polynomial / series chain, so the computed value is
+off by at most ~ c * eps * sum_Z |f(Z)| = c * eps * kappa * |haf|.  The tests
+assert relerr <= C_TOL * eps * kappa with kappa printed by the oracle, plus a
+hard 1e-10 wherever that bound is below it (n <= 24 for Gaussian inputs), and
+exact integers while |haf| * C_TOL * eps * kappa < 1/2.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from gen import inputs as gi
+from oracle import closed_forms as cf
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.0 ** -53
+C_TOL = 64.0
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_values.json")))
+
+
+@pytest.fixture(scope="module")
+def hg():
+    import paper_1805_12498_amd as hg
+    hg.load()
+    print("device:", hg.device_info(), flush=True)
+    return hg
+
+
+_RECORDS = []
+
+
+def record(what, err, kappa):
+    """Keep measured relative errors; written to gpurun_out/parity_errors.json when that folder exists."""
+    _RECORDS.append({"case": what, "relerr": err, "kappa": kappa, "relerr_over_eps_kappa": err / (EPS * kappa)})
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "parity_errors.json"), "w") as f:
+            json.dump(_RECORDS, f, indent=1)
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def gold_value(name):
+    g = GOLD[name]["value"]
+    return oracle.HighPrec((g["re"][0], g["re"][1], g["im"][0], g["im"][1]))
+
+
+def rand_sym(n, seed, scale=0.7):
+    rng = np.random.default_rng(seed)
+    G = rng.normal(0, scale, (n, n)) + 1j * rng.normal(0, scale, (n, n))
+    return (G + G.T) / 2
+
+
+# ---------------------------------------------------------------- small sizes, all kinds
+@pytest.mark.parametrize("n", list(range(0, 17)))
+@pytest.mark.parametrize("kind", [0, 1])
+def test_small_vs_brute_force(hg, n, kind):
+    A = rand_sym(n, 1000 + n)
+    ref = oracle.brute(A, bool(kind)).value
+    got = hg.haf_host(A, kind)
+    if ref == 0:
+        assert got == 0
+    else:
+        assert rel(got, ref) < 1e-12, (n, kind, got, ref)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_config_n16(hg, kind):
+    """16x16 Gaussian symmetric, seed 1601, against the binary128 oracle."""
+    A = gi.gaussian_symmetric(16, gi.SEED_N16)
+    name = "n16_haf" if kind == 0 else "n16_lhaf"
+    ref = gold_value(name)
+    got = hg.haf_host(A, kind)
+    err = ref.relerr(got)
+    kappa = GOLD[name]["kappa"]
+    record("n=16 Gaussian seed 1601 kind=%d" % kind, err, kappa)
+    assert err <= min(1e-10, C_TOL * EPS * kappa)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_config_n40(hg, kind):
+    """40x40 Gaussian symmetric, seed 4001, against the double-double oracle."""
+    name = "n40_haf" if kind == 0 else "n40_lhaf"
+    if name not in GOLD:
+        pytest.skip("oracle value not generated")
+    A = gi.gaussian_symmetric(40, gi.SEED_N40)
+    ref = gold_value(name)
+    got = hg.haf_host(A, kind)
+    err = ref.relerr(got)
+    kappa = GOLD[name]["kappa"]
+    record("n=40 Gaussian seed 4001 kind=%d" % kind, err, kappa)
+    assert err <= C_TOL * EPS * kappa
+
+
+@pytest.mark.parametrize("n,seed", [(20, 1), (24, 2), (28, 3)])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_gaussian_mid_sizes(hg, n, seed, kind):
+    A = gi.gaussian_symmetric(n, seed)
+    ref, kappa = oracle.formula(A, bool(kind), prec="dd", want_kappa=True)
+    err = ref.relerr(hg.haf_host(A, kind))
+    bound = C_TOL * EPS * kappa
+    if n <= 24:
+        bound = min(bound, 1e-10)
+    record("n=%d Gaussian seed %d kind=%d" % (n, seed, kind), err, kappa)
+    assert err <= bound
+
+
+def test_double_double_output(hg):
+    A = gi.gaussian_symmetric(16, gi.SEED_N16)
+    hi_lo = hg.haf_host(A, 0, x2=True)
+    assert hi_lo[0] + hi_lo[1] == hg.haf_host(A, 0).real
+    assert abs(hi_lo[1]) <= abs(hi_lo[0]) * 2 ** -52
+
+
+# ---------------------------------------------------------------- integer inputs
+@pytest.mark.parametrize("n,seed", [(12, 5), (18, 6), (22, 7), (24, 8)])
+def test_random_graph_exact_counts(hg, n, seed):
+    A = gi.random_graph(n, 0.5, seed)
+    exact = oracle.brute_int(A)
+    got = hg.haf_host(A.astype(complex), 0)
+    assert round(got.real) == exact and abs(got.imag) < 0.5
+
+
+@pytest.mark.parametrize("n", [8, 20, 30])
+def test_complete_graph_closed_forms(hg, n):
+    """(n-1)!! and T(n); complete graphs are badly conditioned (kappa ~ 1e7 at n = 30),
+    so the bound is the kappa-scaled one with kappa from the oracle."""
+    for loops, exact in ((False, cf.haf_complete(n)), (True, cf.telephone(n))):
+        A = gi.complete_graph(n, loops=loops).astype(complex)
+        _, kappa = oracle.formula(A, loops, prec="dd", want_kappa=True)
+        err = rel(hg.haf_host(A, int(loops)), exact)
+        record("complete K_%d loops=%d" % (n, loops), err, kappa)
+        assert err <= C_TOL * EPS * kappa
+
+
+def test_grid_and_bipartite(hg):
+    A = gi.grid_graph(4, 6)
+    assert round(hg.haf_host(A.astype(complex), 0).real) == cf.grid_perfect_matchings(4, 6)
+    assert round(hg.haf_host(gi.complete_bipartite(20).astype(complex), 0).real) == math.factorial(10)
+
+
+@pytest.mark.parametrize("n", [12, 20, 28])
+def test_low_rank_inputs(hg, n):
+    """Low-rank B (rank-1 v v^T, rank-2 complete bipartite): after a few reflections the
+    trailing columns are rounding noise, which the reduction must carry without under/overflow."""
+    rng = np.random.default_rng(n)
+    v = rng.normal(size=n) + 1j * rng.normal(size=n)
+    V = np.outer(v, v)
+    V = np.triu(V) + np.triu(V, 1).T          # bitwise symmetric
+    ref, kappa = oracle.formula(V, prec="dd", want_kappa=True)
+    err = ref.relerr(hg.haf_host(V, 0))
+    record("rank-1 n=%d" % n, err, kappa)
+    assert err <= C_TOL * EPS * kappa
+    got = hg.haf_host(gi.complete_bipartite(n).astype(complex), 0)
+    assert rel(got, math.factorial(n // 2)) < 1e-9
+
+
+# ---------------------------------------------------------------- invariances / semantics
+def test_lhaf_zero_diagonal_equals_haf(hg):
+    A = rand_sym(20, 3)
+    np.fill_diagonal(A, 0)
+    assert rel(hg.haf_host(A, 1), hg.haf_host(A, 0)) < 1e-12
+
+
+def test_haf_ignores_diagonal(hg):
+    A = rand_sym(18, 4)
+    B = A.copy()
+    np.fill_diagonal(B, 5.0 - 2j)
+    assert hg.haf_host(A, 0) == hg.haf_host(B, 0)
+
+
+def test_scaling_law(hg):
+    A = rand_sym(16, 5)
+    mu = 1.3
+    assert rel(hg.haf_host(mu * A, 0), mu ** 8 * hg.haf_host(A, 0)) < 1e-11
+    D = np.diag(np.diag(A))
+    assert rel(hg.haf_host(np.sqrt(mu) * D + mu * (A - D), 1), mu ** 8 * hg.haf_host(A, 1)) < 1e-11
+
+
+def test_odd_n(hg):
+    A = rand_sym(9, 6)
+    assert hg.haf_host(A, 0) == 0
+    assert rel(hg.haf_host(A, 1), oracle.brute(A, True).value) < 1e-12
+
+
+def test_bitwise_deterministic(hg):
+    A = gi.gaussian_symmetric(30, 9)
+    a = hg.haf_host(A, 1, x2=True)
+    b = hg.haf_host(A, 1, x2=True)
+    assert a == b
+
+
+def test_errors(hg):
+    from paper_1805_12498_amd._native import HafError
+    A = rand_sym(6, 1)
+    B = A.copy()
+    B[0, 1] += 1e-15
+    with pytest.raises(HafError, match="NOT_SYMMETRIC"):
+        hg.haf_host(B, 0)
+    C = A.copy()
+    C[2, 2] = np.nan
+    with pytest.raises(HafError, match="NONFINITE"):
+        hg.haf_host(C, 0)
+    with pytest.raises(HafError, match="TOO_LARGE"):
+        hg.haf_host(np.zeros((66, 66)), 0)
+    with pytest.raises(HafError, match="TOO_LARGE"):
+        hg.haf_host(np.zeros((65, 65)), 1)
+
+
+# ---------------------------------------------------------------- device API
+def test_device_api_with_torch_stream(hg):
+    import torch
+    A = gi.gaussian_symmetric(24, 11)
+    dA = torch.from_numpy(A).cuda()
+    out = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    st = torch.cuda.current_stream()
+    hg.haf_dev(dA.data_ptr(), 24, 24, out.data_ptr(), st.cuda_stream, kind=0)
+    st.synchronize()
+    assert complex(out.cpu().numpy()[0]) == hg.haf_host(A, 0)
+    # leading dimension larger than n: a 24x24 view inside a 24x30 buffer
+    big = torch.zeros((24, 30), dtype=torch.complex128)
+    big[:, :24] = torch.from_numpy(A)
+    dbig = big.cuda()
+    hg.haf_dev(dbig.data_ptr(), 24, 30, out.data_ptr(), st.cuda_stream, kind=1)
+    st.synchronize()
+    assert complex(out.cpu().numpy()[0]) == hg.haf_host(A, 1)
+
+
+def test_terms_vs_oracle_terms(hg):
+    """Per-subset terms f(Z) at n = 24 against the oracle's per-term route."""
+    import torch
+    n = 24
+    A = gi.gaussian_symmetric(n, 12)
+    rng = np.random.default_rng(0)
+    masks = np.unique(np.concatenate([rng.integers(1, 1 << (n // 2), 40), [1, (1 << (n // 2)) - 1]])).astype(np.uint32)
+    dA = torch.from_numpy(A).cuda()
+    dm = torch.from_numpy(masks.astype(np.int32)).cuda()
+    dt = torch.zeros(len(masks), dtype=torch.complex128, device="cuda")
+    for kind in (0, 1):
+        hg.terms_dev(dA.data_ptr(), n, n, kind, dm.data_ptr(), len(masks), dt.data_ptr(), 0)
+        torch.cuda.synchronize()
+        got = dt.cpu().numpy()
+        for i, m in enumerate(masks):
+            ref = oracle.term(A, int(m), bool(kind), prec="dd").value
+            assert rel(got[i], ref) < 1e-11, (kind, int(m), got[i], ref)
