@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--kind", choices=["haf", "lhaf"], default="haf")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--kernel-path", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -79,6 +80,7 @@ def main():
     dA = torch.from_numpy(A).cuda()
     out = torch.zeros(4, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
+    hg.set_kernel_path(args.kernel_path)
     log("device:", hg.device_info())
 
     def step():

@@ -121,8 +121,10 @@ int haf_batched_c128(const haf_cplx* dA_packed, const int64_t* h_offsets, const 
 /* Free every cached workspace of every device (waits for the device first). */
 int haf_release_workspaces(void);
 
-/* Kernel path selection (for testing): 0 = automatic, 1 = LDS kernel only,
- * 2 = register-tiled kernel wherever its size range allows.  Process-wide. */
+/* Kernel path selection (for testing and tuning): 0 = automatic, 1 = LDS
+ * kernel only, 2 = register-tiled kernels with the default layout table,
+ * 3 = register-tiled kernels with one full wave per matrix above s = 16.
+ * Process-wide. */
 int haf_set_kernel_path(int path);
 
 /* ------------------------------------------------------------------------ */

@@ -78,6 +78,42 @@ __device__ __forceinline__ double wave_max(double x) {
 // Columns whose largest entry is below this are treated as already reduced.
 constexpr double kTinyColumn = 0x1p-960;
 
+// ---------------------------------------------------------------- DPP / swizzle moves of a double
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int PATTERN>
+__device__ __forceinline__ double swizzle_d(double x) {
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), PATTERN);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), PATTERN);
+    return __hiloint2double(hi, lo);
+}
+// value of lane i ^ 32
+__device__ __forceinline__ double xor32_d(double x) {
+    int lo = __double2loint(x), hi = __double2hiint(x);
+    auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    // after the swap the first result holds lanes 0..31 of x twice, the second lanes 32..63 twice
+    const bool upper = (threadIdx.x & 32) != 0;
+    return __hiloint2double(upper ? h[0] : h[1], upper ? l[0] : l[1]);
+}
+
+// Sum over aligned groups of L lanes (L = 4, 8, 16, 32, 64); every lane of a
+// group gets bitwise the same total (each stage adds the same two values).
+template <int L>
+__device__ __forceinline__ double group_sum(double x) {
+    x += dpp_d<0xB1>(x);                    // quad_perm [1,0,3,2]: lane ^ 1
+    x += dpp_d<0x4E>(x);                    // quad_perm [2,3,0,1]: lane ^ 2
+    if (L >= 8) x += dpp_d<0x141>(x);       // row_half_mirror: the other quad of the 8-group
+    if (L >= 16) x += dpp_d<0x140>(x);      // row_mirror: the other 8-group of the row
+    if (L >= 32) x += swizzle_d<0x401F>(x); // lane ^ 16 within 32
+    if (L >= 64) x += xor32_d(x);           // lane ^ 32
+    return x;
+}
+
 // ---------------------------------------------------------------- double-double
 struct dd { double hi, lo; };
 __device__ __forceinline__ dd dd_two_sum(double a, double b) {

@@ -21,12 +21,15 @@ namespace hafgpu {
 template <int SMAX, bool LOOPS>
 __global__ __launch_bounds__(64) void k_coef_lds(const double2* __restrict__ A, int lda, int N, int m,
                                                   uint64_t rank0, int count, const uint32_t* __restrict__ masks,
-                                                  double2* __restrict__ coef, int64_t cstride) {
+                                                  const int* __restrict__ d_exp, double2* __restrict__ coef,
+                                                  int64_t cstride) {
     constexpr int P = SMAX + 1;                 // odd pitch
     __shared__ double2 H[SMAX * P];
     __shared__ double2 vec[SMAX];
     __shared__ int sidx[SMAX];
     const int lane = threadIdx.x;
+    const int e = d_exp ? *d_exp : 0;
+    const double off_scale = ldexp(1.0, -2 * e), diag_scale = ldexp(1.0, -e);
 
     for (int sub = blockIdx.x; sub < count; sub += gridDim.x) {
         const uint32_t mask = masks ? masks[sub] : unrank_subset(rank0 + (uint64_t)sub, m, N);
@@ -46,7 +49,7 @@ __global__ __launch_bounds__(64) void k_coef_lds(const double2* __restrict__ A, 
             const int col = sidx[lane];
             for (int r = 0; r < s; ++r) {
                 const int row = sidx[r] ^ 1;
-                H[r * P + lane] = (lane == (r ^ 1)) ? cz() : A[(int64_t)row * lda + col];
+                H[r * P + lane] = (lane == (r ^ 1)) ? cz() : cscale(A[(int64_t)row * lda + col], off_scale);
             }
         }
         __syncthreads();
@@ -54,7 +57,7 @@ __global__ __launch_bounds__(64) void k_coef_lds(const double2* __restrict__ A, 
         // ---- 2. loop moments
         if (LOOPS) {
             double2 d = cz(), y = cz();
-            if (lane < s) d = A[(int64_t)sidx[lane] * lda + sidx[lane]];
+            if (lane < s) d = cscale(A[(int64_t)sidx[lane] * lda + sidx[lane]], diag_scale);
             y.x = __shfl_xor(d.x, 1, 64);       // (X d)_r = d_{r^1}
             y.y = __shfl_xor(d.y, 1, 64);
             for (int k = 1; k <= N; ++k) {
@@ -149,9 +152,9 @@ __global__ __launch_bounds__(64) void k_coef_lds(const double2* __restrict__ A, 
 // Explicit instantiations (the host selects SMAX >= s).
 #define HAF_INST_LDS(SM)                                                                                   \
     template __global__ void k_coef_lds<SM, false>(const double2*, int, int, int, uint64_t, int,            \
-                                                   const uint32_t*, double2*, int64_t);                     \
+                                                   const uint32_t*, const int*, double2*, int64_t);         \
     template __global__ void k_coef_lds<SM, true>(const double2*, int, int, int, uint64_t, int,             \
-                                                  const uint32_t*, double2*, int64_t);
+                                                  const uint32_t*, const int*, double2*, int64_t);
 HAF_INST_LDS(16)
 HAF_INST_LDS(32)
 HAF_INST_LDS(64)
@@ -161,16 +164,16 @@ HAF_INST_LDS(64)
 namespace hafgpu {
 
 hipError_t launch_coef_lds(int smax, bool loops, int grid, hipStream_t st, const double2* A, int lda, int N,
-                           int m, uint64_t rank0, int count, const uint32_t* masks, double2* coef,
+                           int m, uint64_t rank0, int count, const uint32_t* masks, const int* d_exp, double2* coef,
                            int64_t cstride) {
     if (count <= 0) return hipSuccess;
     if (grid > count) grid = count;
     dim3 g(grid), b(64);
 #define HAF_LAUNCH_LDS(SM)                                                                                  \
     if (loops) hipLaunchKernelGGL((k_coef_lds<SM, true>), g, b, 0, st, A, lda, N, m, rank0, count, masks,   \
-                                  coef, cstride);                                                           \
-    else hipLaunchKernelGGL((k_coef_lds<SM, false>), g, b, 0, st, A, lda, N, m, rank0, count, masks, coef,  \
-                            cstride);
+                                  d_exp, coef, cstride);                                                    \
+    else hipLaunchKernelGGL((k_coef_lds<SM, false>), g, b, 0, st, A, lda, N, m, rank0, count, masks, d_exp, \
+                            coef, cstride);
     if (smax <= 16) { HAF_LAUNCH_LDS(16) }
     else if (smax <= 32) { HAF_LAUNCH_LDS(32) }
     else if (smax <= 64) { HAF_LAUNCH_LDS(64) }

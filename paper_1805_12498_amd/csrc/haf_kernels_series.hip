@@ -61,12 +61,15 @@ __device__ __forceinline__ double2 subset_series(const double2* __restrict__ coe
 template <int N, bool LOOPS>
 __global__ __launch_bounds__(kSeriesBlock) void k_series(const double2* __restrict__ coef, int64_t cstride,
                                                          int count, double sign, double* __restrict__ partials,
-                                                         int64_t slot0, double2* __restrict__ terms) {
+                                                         int64_t slot0, double2* __restrict__ terms,
+                                                         const int* __restrict__ d_exp) {
     const int t = blockIdx.x * kSeriesBlock + threadIdx.x;
     double2 f = cz();
     if (t < count) f = subset_series<N, LOOPS>(coef, cstride, t);
     if (terms) {
-        if (t < count) terms[t] = f;
+        // undo the input scaling: every term is homogeneous of degree N in B
+        const int e2n = d_exp ? 2 * N * (*d_exp) : 0;
+        if (t < count) terms[t] = make_double2(ldexp(f.x, e2n), ldexp(f.y, e2n));
         return;
     }
     __shared__ double sh[4][kSeriesBlock];
@@ -91,8 +94,10 @@ __global__ __launch_bounds__(kSeriesBlock) void k_series(const double2* __restri
 }
 
 #define HAF_INST_SERIES(NN)                                                                                    \
-    template __global__ void k_series<NN, false>(const double2*, int64_t, int, double, double*, int64_t, double2*); \
-    template __global__ void k_series<NN, true>(const double2*, int64_t, int, double, double*, int64_t, double2*);
+    template __global__ void k_series<NN, false>(const double2*, int64_t, int, double, double*, int64_t, double2*, \
+                                                 const int*);                                                 \
+    template __global__ void k_series<NN, true>(const double2*, int64_t, int, double, double*, int64_t, double2*,  \
+                                                const int*);
 HAF_INST_SERIES(1) HAF_INST_SERIES(2) HAF_INST_SERIES(3) HAF_INST_SERIES(4)
 HAF_INST_SERIES(5) HAF_INST_SERIES(6) HAF_INST_SERIES(7) HAF_INST_SERIES(8)
 HAF_INST_SERIES(9) HAF_INST_SERIES(10) HAF_INST_SERIES(11) HAF_INST_SERIES(12)
@@ -106,7 +111,8 @@ HAF_INST_SERIES(29) HAF_INST_SERIES(30) HAF_INST_SERIES(31) HAF_INST_SERIES(32)
 // thread t folds slots t, t+256, ... in order, then a fixed tree.  Writes the
 // double-double result (if out_dd) and its rounding to complex double (if out).
 __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partials, int64_t nslots,
-                                                          double* __restrict__ out_dd, double2* __restrict__ out) {
+                                                          double* __restrict__ out_dd, double2* __restrict__ out,
+                                                          const int* __restrict__ d_exp, int N) {
     __shared__ double sh[4][256];
     const int tid = threadIdx.x;
     dd r{ 0.0, 0.0 }, i{ 0.0, 0.0 };
@@ -126,9 +132,48 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
         __syncthreads();
     }
     if (tid == 0) {
-        if (out_dd) { out_dd[0] = sh[0][0]; out_dd[1] = sh[1][0]; out_dd[2] = sh[2][0]; out_dd[3] = sh[3][0]; }
-        if (out) *out = make_double2(sh[0][0] + sh[1][0], sh[2][0] + sh[3][0]);
+        // undo the exact input scaling: haf(A) = 2^(2eN) haf(A')
+        const int e2n = d_exp ? 2 * N * (*d_exp) : 0;
+        const double rh = ldexp(sh[0][0], e2n), rl = ldexp(sh[1][0], e2n);
+        const double ih = ldexp(sh[2][0], e2n), il = ldexp(sh[3][0], e2n);
+        if (out_dd) { out_dd[0] = rh; out_dd[1] = rl; out_dd[2] = ih; out_dd[3] = il; }
+        if (out) *out = make_double2(rh + rl, ih + il);
     }
+}
+
+// Exponent of the exact input scaling.  With f the largest |Re|, |Im| of an
+// off-diagonal entry, e = floor(ilogb(f) / 2): the off-diagonal part scaled by
+// 2^-2e and the diagonal by 2^-e keep haf and lhaf exact up to the factor
+// 2^(2eN) (the scaling laws of Sec. 2: haf(mu A) = mu^(n/2) haf(A) and
+// lhaf(sqrt(mu) A_diag + mu A_off) = mu^(n/2) lhaf(A)).
+__global__ __launch_bounds__(256) void k_prescale(const double2* __restrict__ A, int n, int lda, int* __restrict__ d_exp) {
+    __shared__ double sh[256];
+    double f = 0.0;
+    for (int e = threadIdx.x; e < n * n; e += 256) {
+        const int i = e / n, j = e % n;
+        if (i != j) {
+            const double2 v = A[(int64_t)i * lda + j];
+            f = fmax(f, fmax(fabs(v.x), fabs(v.y)));
+        }
+    }
+    sh[threadIdx.x] = f;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double m = sh[0];
+        int e = 0;
+        if (m > 0.0 && m <= 1.7e308) e = ilogb(m) >> 1;   // arithmetic shift: floor for negatives too
+        *d_exp = e;
+    }
+}
+
+__global__ void k_scatter(const double2* __restrict__ in, const int* __restrict__ perm, int count,
+                          double2* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[perm[i]] = in[i];
 }
 
 // Write a constant result (n = 0 gives 1, odd n gives 0 for haf).
@@ -158,7 +203,7 @@ namespace hafgpu {
 
 int series_block() { return kSeriesBlock; }
 
-typedef void (*series_fn)(const double2*, int64_t, int, double, double*, int64_t, double2*);
+typedef void (*series_fn)(const double2*, int64_t, int, double, double*, int64_t, double2*, const int*);
 
 #define HAF_SFN(NN) { k_series<NN, false>, k_series<NN, true> },
 static const series_fn g_series[33][2] = {
@@ -171,17 +216,29 @@ static const series_fn g_series[33][2] = {
 #undef HAF_SFN
 
 hipError_t launch_series(int N, bool loops, int count, hipStream_t st, const double2* coef, int64_t cstride,
-                         double sign, double* partials, int64_t slot0, double2* terms) {
+                         double sign, double* partials, int64_t slot0, double2* terms, const int* d_exp) {
     if (N < 1 || N > 32) return hipErrorInvalidValue;
     if (count <= 0) return hipSuccess;
     const int blocks = (count + kSeriesBlock - 1) / kSeriesBlock;
     hipLaunchKernelGGL(g_series[N][loops ? 1 : 0], dim3(blocks), dim3(kSeriesBlock), 0, st, coef, cstride, count,
-                       sign, partials, slot0, terms);
+                       sign, partials, slot0, terms, d_exp);
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(hipStream_t st, const double* partials, int64_t nslots, double* out_dd, double2* out) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partials, nslots, out_dd, out);
+hipError_t launch_reduce(hipStream_t st, const double* partials, int64_t nslots, double* out_dd, double2* out,
+                         const int* d_exp, int N) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, partials, nslots, out_dd, out, d_exp, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(hipStream_t st, const double2* in, const int* perm, int count, double2* out) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3((count + 255) / 256), dim3(256), 0, st, in, perm, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_prescale(hipStream_t st, const double2* A, int n, int lda, int* d_exp) {
+    hipLaunchKernelGGL(k_prescale, dim3(1), dim3(256), 0, st, A, n, lda, d_exp);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -242,12 +243,22 @@ int coef_grid(int dev, int count) {
     return count < g ? count : g;
 }
 
-// Coefficient launches of one chunk.  s = 2m rows per subset.
+// Coefficient launch of one chunk of subsets that all have m pairs (s = 2m
+// rows): ranks rank0.. of the size class, or the given masks.  The
+// register-tiled kernel takes every s it has a layout for; the LDS kernel
+// takes the rest (and everything when forced).
 int launch_coef_chunk(int dev, const double2* dA, int lda, int N, int m, uint64_t rank0, int count,
-                      const uint32_t* masks, int smax, bool loops, double2* coef, int64_t cstride, hipStream_t st) {
-    const int pidx = prof_begin(st, 0, masks ? 0.0 : (double)count * coef_model_flops(2 * m, N, loops), count);
-    hipError_t e = launch_coef_lds(smax, loops, coef_grid(dev, count), st, dA, lda, N, m, rank0, count, masks, coef,
-                                   cstride);
+                      const uint32_t* masks, bool loops, const int* d_exp, double2* coef, int64_t cstride,
+                      hipStream_t st) {
+    const int s = 2 * m;
+    const int pidx = prof_begin(st, 0, (double)count * coef_model_flops(s, N, loops), count);
+    hipError_t e;
+    if (g_kernel_path != 1 && s <= reg_max_s())
+        e = launch_coef_reg(s, loops, device_cus(dev) * 16, st, dA, lda, N, m, rank0, count, masks, d_exp, coef,
+                            cstride, g_kernel_path == 3);
+    else
+        e = launch_coef_lds(s, loops, coef_grid(dev, count), st, dA, lda, N, m, rank0, count, masks, d_exp, coef,
+                            cstride);
     prof_end(pidx, st);
     return hip_check(e, "coefficient kernel launch");
 }
@@ -264,18 +275,21 @@ int enqueue_haf(const double2* dA, int n, int lda, int kind, double* out_dd, dou
     const size_t part_bytes = (size_t)plan.nslots * 4 * sizeof(double);
     if ((rc = workspace_reserve(w, st, coef_bytes, part_bytes, 64))) return rc;
     const bool loops = kind == HAF_KIND_LHAF;
+    int* d_exp = (int*)w->aux;
+    if ((rc = hip_check(launch_prescale(st, dA, n, lda, d_exp), "prescale kernel launch"))) return rc;
     for (const Chunk& c : plan.chunks) {
-        if ((rc = launch_coef_chunk(dev, dA, lda, plan.N, c.m, c.rank0, c.count, nullptr, 2 * c.m, loops, w->coef,
+        if ((rc = launch_coef_chunk(dev, dA, lda, plan.N, c.m, c.rank0, c.count, nullptr, loops, d_exp, w->coef,
                                     c.count, st)))
             return rc;
         const double sign = ((plan.N - c.m) & 1) ? -1.0 : 1.0;
         const int pidx = prof_begin(st, 1, 0.0, c.count);
-        rc = hip_check(launch_series(plan.N, loops, c.count, st, w->coef, c.count, sign, w->part, c.slot0, nullptr),
+        rc = hip_check(launch_series(plan.N, loops, c.count, st, w->coef, c.count, sign, w->part, c.slot0, nullptr,
+                                     nullptr),
                        "series kernel launch");
         prof_end(pidx, st);
         if (rc) return rc;
     }
-    return hip_check(launch_reduce(st, w->part, plan.nslots, out_dd, out), "reduce kernel launch");
+    return hip_check(launch_reduce(st, w->part, plan.nslots, out_dd, out, d_exp, plan.N), "reduce kernel launch");
 }
 
 // Device-side entry: handles n = 0, odd n and the padding for odd-n lhaf.
@@ -362,6 +376,9 @@ int run_host(const haf_cplx* A, int n, int lda, int kind, haf_cplx2* out) {
     return HAF_OK;
 }
 
+// Unsigned terms f(Z) for a list of masks.  The masks are copied to the host
+// and grouped by size so every launch sees one subset size (as in the full
+// sum); results are scattered back to the caller's order.
 int run_terms(const double2* dA, int n, int lda, int kind, const uint32_t* d_masks, int count, double2* d_terms,
               hipStream_t st) {
     int rc = check_dims(dA, n, lda, kind);
@@ -377,16 +394,51 @@ int run_terms(const double2* dA, int n, int lda, int kind, const uint32_t* d_mas
     const int N = n / 2;
     const bool loops = kind == HAF_KIND_LHAF;
     const int ncoef = loops ? 2 * N : N;
-    for (int base = 0; base < count; base += (int)kChunk) {
-        const int cnt = (int)std::min<int64_t>(kChunk, count - base);
-        if ((rc = workspace_reserve(w, st, (size_t)cnt * ncoef * sizeof(double2), 64, 64))) return rc;
-        if ((rc = launch_coef_chunk(dev, dA, lda, N, 0, 0, cnt, d_masks + base, n, loops, w->coef, cnt, st)))
+    std::vector<uint32_t> hm((size_t)count);
+    if ((rc = hip_check(hipMemcpyAsync(hm.data(), d_masks, sizeof(uint32_t) * count, hipMemcpyDeviceToHost, st),
+                        "mask download")))
+        return rc;
+    if ((rc = hip_check(hipStreamSynchronize(st), "stream synchronize"))) return rc;
+    std::vector<int> order((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        if (hm[i] == 0u || (N < 32 && (hm[i] >> N) != 0u))
+            return set_error(HAF_E_INVALID_ARG, "mask %d = %#x is empty or has bits beyond n/2 = %d", i, hm[i], N);
+        order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return __builtin_popcount(hm[x]) < __builtin_popcount(hm[y]); });
+    std::vector<uint32_t> sorted((size_t)count);
+    std::vector<int> perm((size_t)count);
+    for (int i = 0; i < count; ++i) { sorted[i] = hm[order[i]]; perm[i] = order[i]; }
+    // aux: [exponent (256 B)] [sorted masks] [permutation] ; coef: coefficients then terms
+    const size_t off_m = 256, off_p = off_m + ((sizeof(uint32_t) * count + 255) & ~(size_t)255);
+    const size_t aux_need = off_p + sizeof(int) * count;
+    const size_t coef_need = (size_t)count * (ncoef + 1) * sizeof(double2);
+    if ((rc = workspace_reserve(w, st, coef_need, 64, aux_need))) return rc;
+    int* d_exp = (int*)w->aux;
+    uint32_t* d_sorted = (uint32_t*)((char*)w->aux + off_m);
+    int* d_perm = (int*)((char*)w->aux + off_p);
+    if ((rc = hip_check(hipMemcpyAsync(d_sorted, sorted.data(), sizeof(uint32_t) * count, hipMemcpyHostToDevice, st),
+                        "mask upload")))
+        return rc;
+    if ((rc = hip_check(hipMemcpyAsync(d_perm, perm.data(), sizeof(int) * count, hipMemcpyHostToDevice, st),
+                        "permutation upload")))
+        return rc;
+    if ((rc = hip_check(launch_prescale(st, dA, n, lda, d_exp), "prescale kernel launch"))) return rc;
+    double2* tmp_terms = w->coef + (size_t)count * ncoef;
+    for (int i0 = 0; i0 < count;) {
+        const int m = __builtin_popcount(sorted[i0]);
+        int i1 = i0;
+        while (i1 < count && __builtin_popcount(sorted[i1]) == m) ++i1;
+        const int cnt = i1 - i0;
+        if ((rc = launch_coef_chunk(dev, dA, lda, N, m, 0, cnt, d_sorted + i0, loops, d_exp, w->coef + 0, cnt, st)))
             return rc;
-        if ((rc = hip_check(launch_series(N, loops, cnt, st, w->coef, cnt, 1.0, nullptr, 0, d_terms + base),
+        if ((rc = hip_check(launch_series(N, loops, cnt, st, w->coef, cnt, 1.0, nullptr, 0, tmp_terms + i0, d_exp),
                             "series kernel launch")))
             return rc;
+        i0 = i1;
     }
-    return HAF_OK;
+    return hip_check(launch_scatter(st, tmp_terms, d_perm, count, d_terms), "scatter kernel launch");
 }
 
 double now_seconds() {
@@ -477,7 +529,7 @@ int haf_release_workspaces(void) {
 
 int haf_set_kernel_path(int path) {
     clear_error();
-    if (path < 0 || path > 2) return set_error(HAF_E_INVALID_ARG, "kernel path %d not in 0..2", path);
+    if (path < 0 || path > 3) return set_error(HAF_E_INVALID_ARG, "kernel path %d not in 0..3", path);
     set_kernel_path(path);
     return HAF_OK;
 }

@@ -48,7 +48,8 @@ int workspace_reserve(Workspace* w, hipStream_t st, size_t coef_bytes, size_t pa
 int check_dims(const void* p, int n, int lda, int kind);
 int check_values(const haf_cplx* A, int n, int lda);
 int launch_coef_chunk(int dev, const double2* dA, int lda, int N, int m, uint64_t rank0, int count,
-                      const uint32_t* masks, int smax, bool loops, double2* coef, int64_t cstride, hipStream_t st);
+                      const uint32_t* masks, bool loops, const int* d_exp, double2* coef, int64_t cstride,
+                      hipStream_t st);
 int run_dev(const double2* dA, int n, int lda, int kind, double* out_dd, double2* out, hipStream_t st);
 double now_seconds();
 
