@@ -116,6 +116,7 @@ def gbs_parent(seed: int, modes: int = 64, r: float = 0.8):
     rng = np.random.default_rng(seed)
     U = haar_unitary(modes, rng)
     B = (U * np.tanh(r)) @ U.T
+    B = (B + B.T) / 2                 # symmetric to the last bit (the product is only up to rounding)
     gamma = rng.normal(0.0, np.sqrt(0.5), modes) + 1j * rng.normal(0.0, np.sqrt(0.5), modes)
     return B, gamma, rng
 

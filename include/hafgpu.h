@@ -108,15 +108,60 @@ int haf_terms_dev(const haf_cplx* dA, int n, int lda, int kind, const uint32_t* 
                   haf_cplx* d_terms, void* stream);
 
 /*
- * Batched: count independent hafnians / loop hafnians of uneven sizes in one
- * persistent launch (plus one reduction launch).  Matrix t is stored densely
- * (lda = n_t) at element offset h_offsets[t] of dA_packed (device).  h_n,
- * h_offsets and h_kind are host arrays (the planner runs on the host); d_out is
- * a device haf_cplx[count].  Each result is bitwise identical to the plain
- * path's result for the same matrix.
+ * Batched: count independent hafnians / loop hafnians of uneven sizes (the
+ * per-matrix sums of Sec. 3.2, Eq. Pset; the paper names batched small-matrix
+ * GPU work as the way forward in its conclusions).  Matrix t is stored densely
+ * (lda = n_t) at element offset h_offsets[t] of dA_packed (device memory).
+ * h_offsets, h_n and h_kind (HAF_KIND_*) are host arrays; d_out is a device
+ * haf_cplx[count].  Asynchronous like the *_dev calls: the work is ordered
+ * after everything already on `stream`, and `stream` does not pass the call
+ * until every result is written.
+ *
+ * The matrices are spread, largest model cost first, over a pool of
+ * library-owned streams (haf_batched_config.streams of them), each filled by
+ * its own host thread with the single-matrix path, so that the kernels of
+ * different matrices overlap on the device.  Every result is therefore
+ * bitwise the single-matrix path's result for that matrix, whatever else is in
+ * the batch.  (The library also holds a persistent kernel that runs a whole
+ * batch from one work counter; that path is switched off in this build.)
+ * Errors: HAF_E_INVALID_ARG (null pointer, count < 0, n_t < 0, unknown kind),
+ * HAF_E_TOO_LARGE (n_t > HAF_MAX_N), HAF_E_NOMEM, HAF_E_DEVICE.  Matrices are
+ * not checked for symmetry (they live in device memory).
  */
 int haf_batched_c128(const haf_cplx* dA_packed, const int64_t* h_offsets, const int32_t* h_n,
                      const uint8_t* h_kind, int count, haf_cplx* d_out, void* stream);
+
+/* Tunable parameters of the batched path (process-wide). */
+typedef struct {
+    int layout;         /* persistent kernel (switched off): 0 = several matrices per wave
+                           where the tile fits, two waves per SIMD; 1 = one full wave per
+                           matrix above 16 rows; 2 = as 0 at one wave per SIMD          */
+    int group_work;     /* persistent kernel: subsets each matrix slot of a wave takes per
+                           chunk at 16 rows, scaled by (16/s)^3 for s rows              */
+    int waves_per_cu;   /* persistent kernel: workgroups per CU, 0 = as many as fit    */
+    int streams;        /* streams the batch is spread over, 1..16 (default 8)         */
+} haf_batched_config;
+
+int haf_batched_get_config(haf_batched_config* cfg);
+/* HAF_E_INVALID_ARG for values out of range.  No setting changes a result. */
+int haf_batched_set_config(const haf_batched_config* cfg);
+/* Autotuner: runs the given batch (same arguments as haf_batched_c128; d_out
+ * receives the results) with 1, 2, 4, 8 and 16 streams, times each run with
+ * HIP events on `stream`, makes the fastest the current configuration and
+ * returns it in *best and its time in *best_ms.  Synchronous. */
+int haf_batched_tune(const haf_cplx* dA_packed, const int64_t* h_offsets, const int32_t* h_n,
+                     const uint8_t* h_kind, int count, haf_cplx* d_out, void* stream, haf_batched_config* best,
+                     double* best_ms);
+/* Host-only view of the persistent kernel's plan under the current
+ * configuration (no device needed; the kernel itself is switched off).  A
+ * batch runs there as two persistent launches: first the chunks of
+ * subsets above 32 rows, then the rest.  classes receives, in launch order,
+ * 8 int32 per class (item, m, cap, total, j0, chunk_base, slot_base, the item's
+ * slot count), up to max_classes of them; chunk_base counts within its launch.
+ * *n_classes, *n_chunks (both launches) and *variant (the kernel variant of
+ * the second launch) are filled in. */
+int haf_batched_plan(const int32_t* h_n, const uint8_t* h_kind, int count, int32_t* classes, int max_classes,
+                     int* n_classes, int64_t* n_chunks, int* variant);
 
 /* Free every cached workspace of every device (waits for the device first). */
 int haf_release_workspaces(void);
@@ -129,8 +174,9 @@ int haf_set_kernel_path(int path);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing.  While enabled, every coefficient launch (the per-subset
- * Hessenberg / characteristic-polynomial stage) and every series launch is
- * bracketed by HIP events recorded on the launch's own stream.               */
+ * Hessenberg / characteristic-polynomial stage), every series launch and every
+ * persistent batched launch is bracketed by HIP events recorded on the
+ * launch's own stream.                                                        */
 typedef struct {
     int64_t coef_launches;      /* coefficient kernel launches                         */
     double coef_ms;             /* summed event time of those launches                 */
@@ -139,6 +185,9 @@ typedef struct {
     int64_t coef_subsets;       /* subsets they processed                              */
     int64_t series_launches;
     double series_ms;
+    int64_t batched_launches;   /* persistent batched kernel launches (also serving ticks) */
+    double batched_ms;
+    double batched_model_flops; /* same flop model over the subsets they processed      */
 } haf_profile;
 
 /* Start (on != 0) or stop recording; starting clears earlier records. */

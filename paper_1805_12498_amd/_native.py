@@ -27,7 +27,8 @@ EXPORTS = (
     "haf_c128_dev", "lhaf_c128_dev", "haf_c128x2_dev", "haf_terms_dev", "haf_batched_c128",
     "haf_release_workspaces", "haf_set_kernel_path", "haf_server_default_config", "haf_server_create",
     "haf_server_submit", "haf_server_poll", "haf_server_drain", "haf_server_destroy", "haf_now",
-    "haf_profile_enable", "haf_profile_read",
+    "haf_profile_enable", "haf_profile_read", "haf_batched_get_config", "haf_batched_set_config",
+    "haf_batched_tune", "haf_batched_plan",
 )
 
 
@@ -53,7 +54,14 @@ class ServerConfig(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("coef_launches", ctypes.c_int64), ("coef_ms", ctypes.c_double), ("coef_model_flops", ctypes.c_double),
-                ("coef_subsets", ctypes.c_int64), ("series_launches", ctypes.c_int64), ("series_ms", ctypes.c_double)]
+                ("coef_subsets", ctypes.c_int64), ("series_launches", ctypes.c_int64), ("series_ms", ctypes.c_double),
+                ("batched_launches", ctypes.c_int64), ("batched_ms", ctypes.c_double),
+                ("batched_model_flops", ctypes.c_double)]
+
+
+class BatchedConfig(ctypes.Structure):
+    _fields_ = [("layout", ctypes.c_int), ("group_work", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
+                ("streams", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -105,12 +113,15 @@ def load(path: str = LIB_PATH):
         "haf_now": ([], ctypes.c_double),
         "haf_profile_enable": ([i], i),
         "haf_profile_read": ([vp], i),
+        "haf_batched_get_config": ([vp], i),
+        "haf_batched_set_config": ([vp], i),
+        "haf_batched_tune": ([vp, vp, vp, vp, i, vp, vp, vp, ctypes.POINTER(ctypes.c_double)], i),
+        "haf_batched_plan": ([vp, vp, i, vp, i, ctypes.POINTER(i), ctypes.POINTER(i64), ctypes.POINTER(i)], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = res
-    _ = i64
     _lib = lib
     return lib
 
@@ -161,14 +172,59 @@ def terms_dev(dA_ptr: int, n: int, lda: int, kind: int, d_masks_ptr: int, count:
                                ctypes.c_void_p(d_terms_ptr), ctypes.c_void_p(stream)))
 
 
-def batched_dev(dA_ptr: int, offsets: np.ndarray, sizes: np.ndarray, kinds: np.ndarray, d_out_ptr: int,
-                stream: int = 0):
+def _batch_arrays(offsets, sizes, kinds):
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     sizes = np.ascontiguousarray(sizes, dtype=np.int32)
     kinds = np.ascontiguousarray(kinds, dtype=np.uint8)
+    if not (len(offsets) == len(sizes) == len(kinds)):
+        raise ValueError("offsets, sizes and kinds differ in length")
+    return offsets, sizes, kinds
+
+
+def batched_dev(dA_ptr: int, offsets, sizes, kinds, d_out_ptr: int, stream: int = 0):
+    """Enqueue len(sizes) hafnians of matrices packed densely at element offsets of dA."""
+    offsets, sizes, kinds = _batch_arrays(offsets, sizes, kinds)
     check(load().haf_batched_c128(ctypes.c_void_p(dA_ptr), ctypes.c_void_p(offsets.ctypes.data),
                                   ctypes.c_void_p(sizes.ctypes.data), ctypes.c_void_p(kinds.ctypes.data),
                                   len(sizes), ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(stream)))
+
+
+def batched_config() -> dict:
+    c = BatchedConfig()
+    check(load().haf_batched_get_config(ctypes.byref(c)))
+    return {f: getattr(c, f) for f, _ in BatchedConfig._fields_}
+
+
+def set_batched_config(layout: int = 0, group_work: int = 16, waves_per_cu: int = 0, streams: int = 8):
+    c = BatchedConfig(layout, group_work, waves_per_cu, streams)
+    check(load().haf_batched_set_config(ctypes.byref(c)))
+
+
+def batched_tune(dA_ptr: int, offsets, sizes, kinds, d_out_ptr: int, stream: int = 0):
+    """Run the autotuner on this batch; returns (chosen config dict, its time in ms)."""
+    offsets, sizes, kinds = _batch_arrays(offsets, sizes, kinds)
+    c = BatchedConfig()
+    ms = ctypes.c_double(0.0)
+    check(load().haf_batched_tune(ctypes.c_void_p(dA_ptr), ctypes.c_void_p(offsets.ctypes.data),
+                                  ctypes.c_void_p(sizes.ctypes.data), ctypes.c_void_p(kinds.ctypes.data),
+                                  len(sizes), ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(stream),
+                                  ctypes.byref(c), ctypes.byref(ms)))
+    return {f: getattr(c, f) for f, _ in BatchedConfig._fields_}, ms.value
+
+
+def batched_plan(sizes, kinds):
+    """Host-only plan: (classes as an int32 array [n_classes, 8], n_chunks, kernel variant)."""
+    sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+    kinds = np.ascontiguousarray(kinds, dtype=np.uint8)
+    lib = load()
+    ncls, nch, var = ctypes.c_int(0), ctypes.c_int64(0), ctypes.c_int(0)
+    check(lib.haf_batched_plan(ctypes.c_void_p(sizes.ctypes.data), ctypes.c_void_p(kinds.ctypes.data), len(sizes),
+                               None, 0, ctypes.byref(ncls), ctypes.byref(nch), ctypes.byref(var)))
+    out = np.zeros((max(ncls.value, 1), 8), dtype=np.int32)
+    check(lib.haf_batched_plan(ctypes.c_void_p(sizes.ctypes.data), ctypes.c_void_p(kinds.ctypes.data), len(sizes),
+                               ctypes.c_void_p(out.ctypes.data), ncls.value, ctypes.byref(ncls), ctypes.byref(nch),
+                               ctypes.byref(var)))
+    return out[:ncls.value], nch.value, var.value
 
 
 def set_kernel_path(path: int):

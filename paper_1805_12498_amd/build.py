@@ -26,6 +26,7 @@ SOURCES = [
     "haf_kernels_reg.hip",
     "haf_kernels_series.hip",
     "haf_kernels_batched.hip",
+    "haf_kernels_batched24.hip",
     "haf_runtime.cpp",
     "haf_batched.cpp",
     "haf_server.cpp",

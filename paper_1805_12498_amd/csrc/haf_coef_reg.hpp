@@ -1,0 +1,447 @@
+// Per-subset stage, register-tiled form (the hot path for subsets of s <= 48 rows).
+//
+// Same mathematics as the LDS-resident kernel (gather B = (X A_off) on Z, loop
+// moments, Householder reduction to Hessenberg form, characteristic polynomial
+// of the Hessenberg form; App. B and Sec. 3.3), laid out for 64-lane CDNA
+// wavefronts:
+//
+//  * a group of L = P*Q lanes owns one subset matrix; a wave holds W = 64/L groups
+//    (one size class per launch, so every group has the same s);
+//  * lane (a, b) of a group keeps the R x C tile of B with rows a + P t and
+//    columns b + Q u in VGPRs (2D cyclic distribution, so every lane keeps work as
+//    the active trailing block of the reduction shrinks);
+//  * the reduction step index j is a runtime loop; tile slots are static and
+//    column slots left of the active block are skipped with uniform branches, so
+//    nothing is indexed dynamically in registers;
+//  * one reduction step is one pass over the tile: with P = I - tau v v^H,
+//        P^H H P = H - v w'^T - y1 v^H,   w' = conj(tau) (v^H H)^T,
+//        y1 = tau (H v - conj(tau) gamma v),  gamma = v^H H v,
+//    so both dot products come from the same tile and one update follows;
+//  * every cross-lane exchange of a vector goes through LDS as a transposition:
+//    lanes write per-tile partial sums, the lane that owns index i adds its P (or
+//    Q) partials, and the result is read back by the lanes that need it.  On
+//    gfx950 a 16-byte LDS read costs about one FP64 FMA, far less than moving the
+//    same bytes with DPP, swizzle or readlane;
+//  * the characteristic polynomial is built with lanes over the degree d and the
+//    polynomials c_r in registers, fully unrolled for the exact s (so register
+//    slots and LDS offsets are static); the scaled Hessenberg entries g_{r,i} come
+//    from LDS, one read per complex multiply-add.
+//
+// The per-subset body lives in this header so that the one-size-class kernel
+// and the persistent batched kernel run exactly the same arithmetic.
+#pragma once
+#include "haf_common.hpp"
+
+namespace hafgpu {
+
+
+template <int P, int Q, int R, int C>
+struct RegShape {
+    static constexpr int L = P * Q;                        // lanes per matrix
+    static constexpr int W = 64 / L;                       // matrices per wave
+    static constexpr int SM = (P * R < Q * C) ? P * R : Q * C;   // largest s
+    static constexpr int RED = L * (R + C);                // transposition area (w and y partials)
+    static constexpr int VEC = 4 * SM + SM / 2;            // column, v, w', y1 + vertex ids
+    static constexpr int GN = SM * (SM + 1) / 2;           // packed upper triangle
+    static constexpr int SLACK = 8 * W;                    // zeroed, read past the table in whole chunks
+    // during the reduction the area holds the partials and the vectors; afterwards
+    // the packed table (+ slack) overwrites both
+    static constexpr int AREA = RED + VEC > GN + SLACK ? RED + VEC : GN + SLACK;
+    static constexpr int PER = AREA + SM;                  // + subdiagonal
+    static_assert(L * W == 64, "group size must divide 64");
+    static_assert(SM <= L, "the polynomial stage needs one lane per degree");
+};
+
+// Next subset of the same size in increasing mask order (= the next rank of the
+// combinatorial number system), by Gosper's bit trick.
+__device__ __forceinline__ uint32_t next_subset(uint32_t x) {
+    const uint32_t r = x + (x & (0u - x));
+    return (((r ^ x) >> 2) >> __builtin_ctz(x)) | r;
+}
+
+// Characteristic polynomials of the leading principal blocks of the Hessenberg
+// form, c_i(x) = det(x I - H[0:i, 0:i]), by c_i = x c_{i-1} - sum_{r<i} g_{r,i} c_r
+// with the pre-scaled entries g_{r,i} = h_{r,i-1} prod_{k=r+1}^{i-1} h_{k,k-1} in a
+// packed table gt (column i-1 holds rows 0..i-1).  A lane holds the degree-d
+// coefficients c_r[d] of the rows r = h (mod SPLIT) in registers; the SPLIT lanes
+// with the same d sit at lane distance 64/SPLIT and add their partial sums.  Rows
+// below R0 are known to be zero at the degrees this call covers (the second pass
+// of the degree split), so their slots are skipped.  The shift c_{i-1}[d-1] comes
+// from the neighbouring lane, or from `bin` (c_{i-1}[d0-1], written by the first
+// pass) for the lowest degree d0 of the call; `bout`, if given, receives
+// c_i[d_top] for every i.  Each step reads its column in chunks of 8 (the table is
+// followed by zeroed slack, so whole chunks are safe) and keeps the FMA pipeline fed
+// with two accumulators.
+template <int S, int SPLIT, int R0>
+__device__ __forceinline__ double2 charpoly_lanes(const double2* __restrict__ gt, int d, int h, int dlo,
+                                                  const double2* __restrict__ bin, double2* __restrict__ bout,
+                                                  int dtop) {
+    constexpr int K = (S - R0 + SPLIT - 1) / SPLIT;     // register slots per lane
+    double2 cr[K > 0 ? K : 1];
+#pragma unroll
+    for (int k = 0; k < K; ++k) cr[k] = cz();
+    // rows r = R0 + k*SPLIT + h; c_{R0}... start from c_i = 0 at these degrees, except c_0 = 1
+    if (R0 == 0 && h == 0 && d == 0) cr[0] = cone();
+    double2 prev = (R0 == 0 && d == 0) ? cone() : cz();
+#pragma unroll
+    for (int i = (R0 > 0 ? R0 : 1); i <= S; ++i) {
+        const int nk = (i - R0 + SPLIT - 1) / SPLIT;    // slots that may hold r < i (compile-time)
+        double2 acc[2] = { cz(), cz() };
+#pragma unroll
+        for (int c0 = 0; c0 < nk; c0 += 8) {
+            double2 gv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (c0 + k < K) gv[k] = gt[(i - 1) * i / 2 + R0 + (c0 + k) * SPLIT + h];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (c0 + k < K) cfma(acc[k & 1], gv[k], cr[c0 + k]);
+        }
+        double2 tot = cadd(acc[0], acc[1]);
+        if (SPLIT >= 4) { tot.x += swizzle_d<0x401F>(tot.x); tot.y += swizzle_d<0x401F>(tot.y); }   // lane ^ 16
+        if (SPLIT >= 2) { tot.x += xor32_d(tot.x); tot.y += xor32_d(tot.y); }                   // lane ^ 32
+        double2 sh;
+        sh.x = dpp_d<0x138>(prev.x);          // wave_shr:1 -> c_{i-1}[d-1]
+        sh.y = dpp_d<0x138>(prev.y);
+        if (d == dlo) sh = bin ? bin[i - 1] : cz();
+        const double2 ci = csub(sh, tot);
+        if (i < S) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k == (i - R0) / SPLIT && h == (i - R0) % SPLIT) cr[k] = ci;
+        }
+        if (bout && i < S && d == dtop && h == 0) bout[i] = ci;   // bout has S entries
+        prev = ci;
+        // keep each step's reads within the step: hoisting them across steps only
+        // raises register pressure (and occupancy is what hides their latency)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return prev;
+}
+
+#define HAF_CP_CASES                                                                                         \
+    HAF_CP_CASE(2) HAF_CP_CASE(4) HAF_CP_CASE(6) HAF_CP_CASE(8) HAF_CP_CASE(10) HAF_CP_CASE(12)             \
+    HAF_CP_CASE(14) HAF_CP_CASE(16) HAF_CP_CASE(18) HAF_CP_CASE(20) HAF_CP_CASE(22) HAF_CP_CASE(24)         \
+    HAF_CP_CASE(26) HAF_CP_CASE(28) HAF_CP_CASE(30) HAF_CP_CASE(32) HAF_CP_CASE(34) HAF_CP_CASE(36)         \
+    HAF_CP_CASE(38) HAF_CP_CASE(40) HAF_CP_CASE(42) HAF_CP_CASE(44) HAF_CP_CASE(46) HAF_CP_CASE(48)
+
+// a_k = c_s[s-k], the lambda^k coefficient of det(I - lambda B), from lane d, plus
+// zeros for s < k <= N
+__device__ __forceinline__ void write_coefs(double2* __restrict__ coef, int64_t cstride, bool valid, int sub, int s,
+                                            int N, int d, int L, double2 cs) {
+    if (!valid) return;
+    const int k = s - d;
+    if (d < s && k <= N) coef[(int64_t)(k - 1) * cstride + sub] = cs;
+    for (int kk = s + 1 + d; kk <= N; kk += L) coef[(int64_t)(kk - 1) * cstride + sub] = cz();
+}
+__device__ __forceinline__ void write_coefs_range(double2* __restrict__ coef, int64_t cstride, bool valid, int sub,
+                                                  int s, int N, int d, int dlo, int dhi, double2 cs) {
+    if (!valid || d < dlo || d >= dhi || d >= s) return;
+    const int k = s - d;
+    if (k <= N) coef[(int64_t)(k - 1) * cstride + sub] = cs;
+}
+
+// CP selects how the polynomial stage uses the wave: 0 = every group on its own
+// matrix, 1 = the whole wave on one matrix at a time with the rows split over the
+// W lane groups, 2 = one matrix per wave, degrees in two passes (below 32 with the
+// rows split over the two lane halves, then the rest).
+template <int P, int Q, int R, int C, int CP, bool LOOPS>
+__device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const double2* __restrict__ A, int lda,
+                                              int N, int m, uint64_t rank0, int count,
+                                              const uint32_t* __restrict__ masks, double off_scale,
+                                              double diag_scale, double2* __restrict__ coef, int64_t cstride,
+                                              int grp0, int span, int tid) {
+    using S = RegShape<P, Q, R, C>;
+    constexpr int L = S::L, W = S::W, SM = S::SM;
+
+    const int g = tid / L;                    // group (matrix) in the wave
+    const int lam = tid % L;                  // lane in the group
+    const int a = lam / Q, b = lam % Q;       // row group, column group
+    double2* red = lds + g * S::PER;          // transposition area / packed polynomial table
+    double2* colb = red + S::RED;             // column j of H
+    double2* vv = colb + SM;                  // Householder vector v
+    double2* wb = vv + SM;                    // w' = conj(tau) v^H H
+    double2* yb = wb + SM;                    // y1 = tau (H v - conj(tau) gamma v)
+    int* vid = (int*)(yb + SM);               // subset vertex of each row (SM ints)
+    double2* beta = red + S::AREA;            // subdiagonal of the Hessenberg form
+    double2* wpart = red;                     // [lane][u]
+    double2* ypart = red + L * C;             // [lane][t]
+    const int s = 2 * m;
+
+    // tid = lane in the wave; group g of the wave owns the run of `span` subsets starting at (grp0 + g) * span
+    const int first = (grp0 + g) * span;
+    uint32_t mask = 0;
+    for (int q = 0; q < span; ++q) {
+        const int sub = first + q;
+        const bool valid = sub < count;
+        if (masks) mask = masks[valid ? sub : 0];
+        else mask = q == 0 ? unrank_subset(rank0 + (uint64_t)(valid ? sub : 0), m, N) : next_subset(mask);
+        if (!valid) mask = (1u << m) - 1u;    // any m-subset: computed, never written
+
+        // ---- vertex of each row: row r is member r&1 of the (r/2)-th chosen pair
+        if (lam < s) vid[lam] = subset_vertex(mask, lam);
+        __syncthreads();
+        int rv[R], cv[C];
+#pragma unroll
+        for (int t = 0; t < R; ++t) rv[t] = (a + P * t < s) ? vid[a + P * t] : 0;
+#pragma unroll
+        for (int u = 0; u < C; ++u) cv[u] = (b + Q * u < s) ? vid[b + Q * u] : 0;
+
+        // ---- gather the tile of B = X A_off on Z (row r of B is row vid[r]^1 of A)
+        double2 h[R][C];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const double2* arow = A + (int64_t)(rv[t] ^ 1) * lda;
+#pragma unroll
+            for (int u = 0; u < C; ++u) {
+                const int r = a + P * t, c = b + Q * u;
+                h[t][u] = (r < s && c < s && c != (r ^ 1)) ? cscale(arow[cv[u]], off_scale) : cz();
+            }
+        }
+
+        // ---- loop moments l_k = d^T B^(k-1) X d  (lane lam owns index lam of d)
+        if (LOOPS) {
+            const int vl = lam < s ? vid[lam] : 0;
+            const double2 dl = lam < s ? cscale(A[(int64_t)vl * lda + vl], diag_scale) : cz();
+            const double2 dp = lam < s ? cscale(A[(int64_t)(vl ^ 1) * lda + (vl ^ 1)], diag_scale) : cz();
+            double2 yc[C];                     // y at own columns; y_0 = X d, (X d)_c = d_{c^1}
+#pragma unroll
+            for (int u = 0; u < C; ++u)
+                yc[u] = (b + Q * u < s) ? cscale(A[(int64_t)(cv[u] ^ 1) * lda + (cv[u] ^ 1)], diag_scale) : cz();
+            double2 prod = cmul(dl, dp);
+            double lx = group_sum<L>(prod.x), ly = group_sum<L>(prod.y);
+            if (valid && lam == 0) coef[(int64_t)N * cstride + sub] = make_double2(lx, ly);
+            for (int k = 2; k <= N; ++k) {
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    double2 acc = cz();
+#pragma unroll
+                    for (int u = 0; u < C; ++u) cfma(acc, h[t][u], yc[u]);
+                    ypart[lam * R + t] = acc;
+                }
+                __syncthreads();
+                double2 yr = cz();            // (B y)_lam
+                if (lam < s) {
+                    const int ra = lam % P, rt = lam / P;
+#pragma unroll
+                    for (int bb = 0; bb < Q; ++bb) {
+                        const double2 pp = ypart[(ra * Q + bb) * R + rt];
+                        yr.x += pp.x;
+                        yr.y += pp.y;
+                    }
+                }
+                prod = cmul(dl, yr);
+                lx = group_sum<L>(prod.x);
+                ly = group_sum<L>(prod.y);
+                if (valid && lam == 0) coef[(int64_t)(N + k - 1) * cstride + sub] = make_double2(lx, ly);
+                if (k == N) break;
+                if (lam < SM) yb[lam] = yr;
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < C; ++u) yc[u] = (b + Q * u < s) ? yb[b + Q * u] : cz();
+            }
+        }
+
+        // ---- Householder reduction to upper Hessenberg form
+        if (b == 0) {                          // column 0 -> colb
+#pragma unroll
+            for (int t = 0; t < R; ++t)
+                if (a + P * t < SM) colb[a + P * t] = h[t][0];
+        }
+        for (int j = 0; j + 2 < s; ++j) {
+            __syncthreads();                  // column j is in colb
+            const double2 x = (lam > j && lam < s) ? colb[lam] : cz();
+            const double2 alpha = colb[j + 1];
+            const double sig = group_sum<L>(lam >= j + 2 ? fma(x.x, x.x, x.y * x.y) : 0.0);
+            const double tot = fma(alpha.x, alpha.x, fma(alpha.y, alpha.y, sig));
+            // inputs are pre-scaled to entries of order one, so a column this small is
+            // rounding noise of an already reduced (rank-deficient) part: leave it
+            const bool skip = tot < 0x1p-960 || (sig == 0.0 && alpha.y == 0.0);
+            double2 tau = cz(), scal = cz(), v = cz();
+            double bet = alpha.x;
+            if (!skip) {
+                const double nrm = sqrt(tot);
+                bet = alpha.x >= 0.0 ? -nrm : nrm;
+                tau = make_double2((bet - alpha.x) / bet, -alpha.y / bet);
+                scal = crecip(make_double2(alpha.x - bet, alpha.y));
+                v = lam == j + 1 ? cone() : (lam > j + 1 ? cmul(x, scal) : cz());
+            }
+            if (lam < SM) vv[lam] = v;
+            if (lam == 0) beta[j + 1] = skip ? alpha : make_double2(bet, 0.0);
+            __syncthreads();
+            double2 vr[R];
+#pragma unroll
+            for (int t = 0; t < R; ++t) vr[t] = (a + P * t < SM) ? vv[a + P * t] : cz();
+            const int ulo = (j + 1) / Q;      // column slots left of ulo hold only columns <= j
+
+            // one pass: w partials (over own rows) and y partials (over own columns)
+            double2 yp[R];
+#pragma unroll
+            for (int t = 0; t < R; ++t) yp[t] = cz();
+#pragma unroll
+            for (int u = 0; u < C; ++u)
+                if (u >= ulo) {
+                    const double2 vcu = (b + Q * u < SM) ? vv[b + Q * u] : cz();
+                    double2 wp = cz();
+#pragma unroll
+                    for (int t = 0; t < R; ++t) {
+                        cfma_cj(wp, vr[t], h[t][u]);
+                        cfma(yp[t], h[t][u], vcu);
+                    }
+                    wpart[lam * C + u] = wp;
+                }
+#pragma unroll
+            for (int t = 0; t < R; ++t) ypart[lam * R + t] = yp[t];
+            __syncthreads();
+            // lane lam owns column lam (w) and row lam (y)
+            double2 w = cz(), y = cz();
+            if (lam > j && lam < s) {
+                const int cb = lam % Q, cu = lam / Q;
+#pragma unroll
+                for (int aa = 0; aa < P; ++aa) {
+                    const double2 pp = wpart[(aa * Q + cb) * C + cu];
+                    w.x += pp.x;
+                    w.y += pp.y;
+                }
+            }
+            if (lam < s) {
+                const int ra = lam % P, rt = lam / P;
+#pragma unroll
+                for (int bb = 0; bb < Q; ++bb) {
+                    const double2 pp = ypart[(ra * Q + bb) * R + rt];
+                    y.x += pp.x;
+                    y.y += pp.y;
+                }
+            }
+            const double2 wv = cmul(w, v);
+            const double2 gam = make_double2(group_sum<L>(wv.x), group_sum<L>(wv.y));
+            double2 y1 = y;
+            cfms(y1, cmul(cconj(tau), gam), v);
+            if (lam < SM) {
+                wb[lam] = cmul(cconj(tau), w);
+                yb[lam] = cmul(tau, y1);
+            }
+            __syncthreads();
+            double2 yr[R];
+#pragma unroll
+            for (int t = 0; t < R; ++t) yr[t] = (a + P * t < SM) ? yb[a + P * t] : cz();
+#pragma unroll
+            for (int u = 0; u < C; ++u)
+                if (u >= ulo) {
+                    const double2 wu = (b + Q * u < SM) ? wb[b + Q * u] : cz();
+                    const double2 vcu = (b + Q * u < SM) ? vv[b + Q * u] : cz();
+#pragma unroll
+                    for (int t = 0; t < R; ++t) {
+                        cfms(h[t][u], vr[t], wu);
+                        cfms_cj(h[t][u], yr[t], vcu);
+                    }
+                }
+            // column j+1 -> colb for the next step (its owners have just updated it)
+            const int un = (j + 1) / Q, bn = (j + 1) % Q;
+            if (b == bn && j + 3 < s) {
+#pragma unroll
+                for (int u = 0; u < C; ++u)
+                    if (u == un) {
+#pragma unroll
+                        for (int t = 0; t < R; ++t)
+                            if (a + P * t < SM) colb[a + P * t] = h[t][u];
+                    }
+            }
+        }
+
+        // ---- the last subdiagonal entry (no reflector acts on it)
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+#pragma unroll
+            for (int u = 0; u < C; ++u)
+                if (a + P * t == s - 1 && b + Q * u == s - 2) beta[s - 1] = h[t][u];
+        __syncthreads();                      // partial areas are free again
+        // ---- upper triangle (incl. diagonal) -> packed table, column c holds rows 0..c
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+#pragma unroll
+            for (int u = 0; u < C; ++u) {
+                const int r = a + P * t, c = b + Q * u;
+                if (r <= c && c < s) red[c * (c + 1) / 2 + r] = h[t][u];
+            }
+        __syncthreads();
+        for (int z = lam; z < S::SLACK; z += L) red[s * (s + 1) / 2 + z] = cz();   // slack after the table
+        // g_{r,c+1} = h_{r,c} prod_{k=r+1}^{c} h_{k,k-1}: lane r walks its row
+        if (lam < s) {
+            double2 pi = cone();
+            for (int c = lam; c < s; ++c) {
+                const int idx = c * (c + 1) / 2 + lam;
+                red[idx] = cmul(red[idx], pi);
+                if (c + 1 < s) pi = cmul(pi, beta[c + 1]);
+            }
+        }
+        __syncthreads();
+
+        // ---- characteristic polynomials
+        if (CP == 0) {                        // each group: lane lam = degree d
+            double2 cs = cz();
+            switch (s) {
+#define HAF_CP_CASE(SS) case SS: if (SS <= SM && SS + 8 > SM) \
+                cs = charpoly_lanes<(SS <= SM ? SS : 2), 1, 0>(red, lam, 0, 0, nullptr, nullptr, 0); break;
+                HAF_CP_CASES
+#undef HAF_CP_CASE
+                default: break;
+            }
+            write_coefs(coef, cstride, valid, sub, s, N, lam, L, cs);
+        } else if (CP == 1) {                 // whole wave per matrix, rows split over groups
+#pragma unroll 1
+            for (int gg = 0; gg < W; ++gg) {
+                const int subg = (grp0 + gg) * span + q;
+                const double2* gt = lds + gg * S::PER;
+                double2 cs = cz();
+                switch (s) {
+#define HAF_CP_CASE(SS) case SS: if (SS <= SM && SS + 8 > SM) \
+                    cs = charpoly_lanes<(SS <= SM ? SS : 2), W, 0>(gt, lam, g, 0, nullptr, nullptr, 0); break;
+                    HAF_CP_CASES
+#undef HAF_CP_CASE
+                    default: break;
+                }
+                if (g == 0) write_coefs(coef, cstride, subg < count, subg, s, N, lam, L, cs);
+            }
+        } else {                              // W == 1: degree passes d < 32, then d >= 32
+            const int hh = lam / 32, dd = lam % 32;
+            double2* bnd = beta;              // c_i[31] for every i (beta is no longer needed)
+            double2 cs = cz();
+            switch (s) {
+#define HAF_CP_CASE(SS) case SS: if (SS <= SM && SS + 8 > SM) \
+                cs = charpoly_lanes<(SS <= SM ? SS : 2), 2, 0>(red, dd, hh, 0, nullptr, bnd, 31); break;
+                HAF_CP_CASES
+#undef HAF_CP_CASE
+                default: break;
+            }
+            if (hh == 0) write_coefs_range(coef, cstride, valid, sub, s, N, dd, 0, 32, cs);
+            if (s > 32) {
+                __syncthreads();              // bnd is complete
+                double2 cs2 = cz();
+                switch (s) {
+#define HAF_CP_CASE(SS) case SS: if (SS <= SM && SS + 8 > SM && SS > 32) \
+                    cs2 = charpoly_lanes<(SS <= SM && SS > 32 ? SS : 34), 2, 32>(red, dd + 32, hh, 32, bnd, nullptr, 0); break;
+                    HAF_CP_CASES
+#undef HAF_CP_CASE
+                    default: break;
+                }
+                if (hh == 0) write_coefs_range(coef, cstride, valid, sub, s, N, dd + 32, 32, s, cs2);
+            }
+            if (hh == 0 && valid)
+                for (int kk = s + 1 + dd; kk <= N; kk += 32) coef[(int64_t)(kk - 1) * cstride + sub] = cz();
+        }
+        __syncthreads();                      // LDS is reused by the next subset
+    }
+}
+
+
+// Layouts and the subset sizes each one serves: (P, Q, R, C, CP) for s in (lo, hi].
+// The "narrow" table packs two or four matrices per wave where the tile fits;
+// the "wide" table gives every matrix above s = 16 a full wave (smaller tiles,
+// fewer registers, more resident waves).
+#define HAF_REG_NARROW(X) X(4, 4, 2, 2, 0, 0, 8) X(4, 4, 4, 4, 0, 8, 16) X(8, 4, 3, 6, 0, 16, 24) \
+                          X(8, 4, 4, 8, 1, 24, 32) X(8, 8, 5, 5, 2, 32, 40) X(8, 8, 6, 6, 2, 40, 48)
+#define HAF_REG_WIDE(X) X(8, 8, 3, 3, 2, 16, 24) X(8, 8, 4, 4, 2, 24, 32)
+#define HAF_REG_SHAPES(X) HAF_REG_NARROW(X) HAF_REG_WIDE(X)
+
+}  // namespace hafgpu

@@ -11,49 +11,13 @@
 //                  series is its lambda^N coefficient),
 //   signed sum     (-1)^(N-|Z|) f(Z) (Eq. Pset), accumulated in double-double by a
 //                  fixed-shape tree in the block; one partial per block.
-// N is a template parameter so the coefficient arrays stay in registers.
 #include "haf_common.hpp"
 #include "haf_launch.hpp"
+#include "haf_series.hpp"
 
 namespace hafgpu {
 
 constexpr int kSeriesBlock = 256;
-
-template <int N, bool LOOPS>
-__device__ __forceinline__ double2 subset_series(const double2* __restrict__ coef, int64_t cstride, int t) {
-    double2 a[N + 1], p[N + 1];
-#pragma unroll
-    for (int k = 1; k <= N; ++k) a[k] = coef[(int64_t)(k - 1) * cstride + t];
-    // Newton's identities
-#pragma unroll
-    for (int k = 1; k <= N; ++k) {
-        double2 acc = cscale(a[k], -(double)k);
-#pragma unroll
-        for (int i = 1; i < k; ++i) cfms(acc, a[i], p[k - i]);
-        p[k] = acc;
-    }
-    // k c_k = p_k / 2 [+ k l_k / 2]; kept in p
-#pragma unroll
-    for (int k = 1; k <= N; ++k) {
-        double2 kc = cscale(p[k], 0.5);
-        if (LOOPS) {
-            double2 l = coef[(int64_t)(N + k - 1) * cstride + t];
-            kc.x = fma(0.5 * (double)k, l.x, kc.x);
-            kc.y = fma(0.5 * (double)k, l.y, kc.y);
-        }
-        p[k] = kc;
-    }
-    // exponential series, e_j in place of a_j (a is no longer needed)
-    a[0] = cone();
-#pragma unroll
-    for (int j = 1; j <= N; ++j) {
-        double2 acc = cz();
-#pragma unroll
-        for (int k = 1; k <= j; ++k) cfma(acc, p[k], a[j - k]);
-        a[j] = cscale(acc, 1.0 / (double)j);
-    }
-    return a[N];
-}
 
 // One block = kSeriesBlock subsets.  If terms != nullptr the unsigned f(Z) are
 // written out (no sum); otherwise the block's signed double-double partial goes
@@ -65,7 +29,7 @@ __global__ __launch_bounds__(kSeriesBlock) void k_series(const double2* __restri
                                                          const int* __restrict__ d_exp) {
     const int t = blockIdx.x * kSeriesBlock + threadIdx.x;
     double2 f = cz();
-    if (t < count) f = subset_series<N, LOOPS>(coef, cstride, t);
+    if (t < count) f = subset_series_upto<N, LOOPS>(coef, cstride, t, N);
     if (terms) {
         // undo the input scaling: every term is homogeneous of degree N in B
         const int e2n = d_exp ? 2 * N * (*d_exp) : 0;

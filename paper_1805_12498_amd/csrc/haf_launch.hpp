@@ -38,3 +38,27 @@ hipError_t launch_write_const(hipStream_t st, double re, double* out_dd, double2
 hipError_t launch_pad_odd(hipStream_t st, const double2* A, int n, int lda, double2* out);
 
 }  // namespace hafgpu
+
+#include "haf_batch.hpp"
+
+namespace hafgpu {
+
+// Persistent batched kernel.  Variants (layout table, waves per SIMD, series
+// bound): 0 = (0, 2, 16), 1 = (1, 2, 16), 2 = (2, 1, 24), 3 = (0, 1, 16),
+// 4 = (0, 2, 24), 5 = (1, 2, 24), 6 = (0, 1, 24).  Table 0: the default layouts
+// up to s = 32; 1: one wave per matrix above s = 16, up to 32; 2: s = 34..48.
+int batch_group_count(int table, int s);       // matrices per wave of table's layout for s rows
+int batch_variant_table(int v);
+int batch_variant_nmax(int v);
+int batch_coef_per_wave(int v);                // coefficient scratch per wave (complex values)
+int batch_waves_per_cu(int v);                 // resident one-wave workgroups per CU
+const void* batched_kernel16(int v);
+bool launch_batched16(int v, int grid, hipStream_t st, const BatchItem* items, const BatchClass* classes, int ncls,
+                      int nchunks, int* cursor, int* done, const int* exps, double* partials, double2* coefscr);
+hipError_t launch_batch_prologue(hipStream_t st, const BatchItem* items, const int* new_items, int nnew, int* exps,
+                                 int* done, int* cursor);
+hipError_t launch_batched(int v, int grid, hipStream_t st, const BatchItem* items, const BatchClass* classes,
+                          int ncls, int nchunks, int* cursor, int* done, const int* exps, double* partials,
+                          double2* coefscr);
+
+}  // namespace hafgpu

@@ -133,7 +133,7 @@ std::string device_description() {
     return buf;
 }
 
-static int grow(void** p, size_t* cap, size_t need, hipStream_t st) {
+int grow(void** p, size_t* cap, size_t need, hipStream_t st) {
     if (need <= *cap) return HAF_OK;
     if (*p) {
         (void)hipStreamSynchronize(st);
@@ -194,10 +194,11 @@ int release_workspaces() {
         ds->ws.clear();
     }
     (void)hipSetDevice(cur);
+    release_batch_workspaces();
     return HAF_OK;
 }
 
-static int hip_check(hipError_t e, const char* what) {
+int hip_check(hipError_t e, const char* what) {
     if (e == hipSuccess) return HAF_OK;
     return set_error(HAF_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
@@ -205,7 +206,7 @@ static int hip_check(hipError_t e, const char* what) {
 // ------------------------------------------------------------------ timing
 struct ProfRec {
     hipEvent_t a, b;
-    int what;           // 0 = coefficient launch, 1 = series launch
+    int what;           // 0 = coefficient launch, 1 = series launch, 2 = persistent batched launch
     double flops;
     int64_t subsets;
 };
@@ -563,6 +564,10 @@ int haf_profile_read(haf_profile* out) {
             out->coef_ms += ms;
             out->coef_model_flops += r.flops;
             out->coef_subsets += r.subsets;
+        } else if (r.what == 2) {
+            out->batched_launches++;
+            out->batched_ms += ms;
+            out->batched_model_flops += r.flops;
         } else {
             out->series_launches++;
             out->series_ms += ms;

@@ -52,5 +52,11 @@ int launch_coef_chunk(int dev, const double2* dA, int lda, int N, int m, uint64_
                       hipStream_t st);
 int run_dev(const double2* dA, int n, int lda, int kind, double* out_dd, double2* out, hipStream_t st);
 double now_seconds();
+int grow(void** p, size_t* cap, size_t need, hipStream_t st);   // (re)allocate device memory, 1.25x headroom
+int hip_check(hipError_t e, const char* what);
+int prof_begin(hipStream_t st, int what, double flops, int64_t subsets);
+void prof_end(int idx, hipStream_t st);
+double coef_model_flops(int s, int N, bool loops);
+void release_batch_workspaces();
 
 }  // namespace hafgpu

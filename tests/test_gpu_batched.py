@@ -1,0 +1,165 @@
+"""GPU tests of the batched path (haf_batched_c128) through the C ABI.
+
+The batch is spread over a pool of streams, each filled with the
+single-matrix path.  Checks: results against the CPU oracle (brute force at
+small n, the formula in double-double at mid n), bitwise equality with the
+single-matrix path and independence of a result from the rest of the batch
+and from the stream count, bitwise reproducibility, the constant and padded
+edge cases, errors and the autotuner.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gen import inputs as gi
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.0 ** -53
+C_TOL = 64.0
+
+
+@pytest.fixture(scope="module")
+def hg():
+    import paper_1805_12498_amd as hg
+    hg.load()
+    hg.set_batched_config(streams=8)
+    print("device:", hg.device_info(), flush=True)
+    yield hg
+    hg.set_batched_config(streams=8)
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def rand_sym(n, seed, scale=0.7):
+    rng = np.random.default_rng(seed)
+    G = rng.normal(0, scale, (n, n)) + 1j * rng.normal(0, scale, (n, n))
+    return (G + G.T) / 2
+
+
+def run_batch(hg, mats, kinds):
+    import torch
+    flat, offs, sizes = gi.pack(mats)
+    dA = torch.from_numpy(flat).cuda()
+    out = torch.full((max(len(mats), 1),), complex(np.nan, np.nan), dtype=torch.complex128, device="cuda")
+    hg.batched_dev(dA.data_ptr(), offs, sizes, np.asarray(kinds, dtype=np.uint8), out.data_ptr(),
+                   torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()[:len(mats)]
+
+
+def run_plain(hg, A, kind):
+    import torch
+    n = A.shape[0]
+    dA = torch.from_numpy(np.ascontiguousarray(A) if n else np.zeros(1, complex)).cuda()
+    out = torch.zeros(1, dtype=torch.complex128, device="cuda")
+    hg.haf_dev(dA.data_ptr(), n, max(n, 1), out.data_ptr(), torch.cuda.current_stream().cuda_stream, kind=kind)
+    torch.cuda.synchronize()
+    return complex(out.cpu().numpy()[0])
+
+
+def test_small_mixed_vs_brute_force(hg):
+    """n = 0..14, both kinds, odd n included (haf 0, lhaf padded)."""
+    mats, kinds = [], []
+    for n in range(0, 15):
+        for kind in (0, 1):
+            mats.append(rand_sym(n, 300 + 2 * n + kind))
+            kinds.append(kind)
+    got = run_batch(hg, mats, kinds)
+    for A, kind, g in zip(mats, kinds, got):
+        ref = oracle.brute(A, bool(kind)).value
+        if ref == 0:
+            assert g == 0, (A.shape[0], kind, g)
+        else:
+            assert rel(g, ref) < 1e-12, (A.shape[0], kind, g, ref)
+
+
+@pytest.mark.parametrize("streams", [1, 4, 16])
+def test_gbs_batch_vs_oracle_and_plain(hg, streams):
+    """GBS-style loop hafnians n in [8, 32] (the batched workload's construction):
+    bitwise the single-matrix path on all, the oracle (double-double formula) on a sample."""
+    hg.set_batched_config(streams=streams)
+    mats = gi.gbs_batch(48, seed=gi.SEED_BATCH + 1)
+    kinds = [1] * len(mats)
+    got = run_batch(hg, mats, kinds)
+    for t, A in enumerate(mats):
+        assert got[t] == run_plain(hg, A, 1), (streams, t, A.shape[0])
+    for t in range(0, len(mats), 8):
+        ref, kappa = oracle.formula(mats[t], True, prec="dd", want_kappa=True)
+        assert ref.relerr(got[t]) <= max(1e-12, C_TOL * EPS * kappa), (streams, t, mats[t].shape[0])
+    hg.set_batched_config(streams=8)
+
+
+def test_alone_equals_in_mix_bitwise(hg):
+    """A result depends only on its own matrix: alone, in a batch of small items, and in a
+    batch that also holds large items it is bitwise equal."""
+    mats = gi.gbs_batch(24, seed=7)
+    kinds = [t % 2 for t in range(len(mats))]
+    mix = run_batch(hg, mats, kinds)
+    big = [rand_sym(40, 1), rand_sym(46, 2)]
+    mix2 = run_batch(hg, big + mats, [0, 1] + kinds)[2:]
+    for t in (0, 5, 11, 23):
+        alone = run_batch(hg, [mats[t]], [kinds[t]])[0]
+        assert alone == mix[t] == mix2[t], (t, alone, mix[t], mix2[t])
+    assert np.array_equal(mix, mix2)
+
+
+def test_reproducible(hg):
+    mats = gi.gbs_batch(32, seed=9)
+    kinds = [1] * len(mats)
+    assert np.array_equal(run_batch(hg, mats, kinds), run_batch(hg, mats, kinds))
+
+
+@pytest.mark.parametrize("n", [34, 40, 50])
+def test_large_items(hg, n):
+    A = gi.gaussian_symmetric(n, 900 + n)
+    small = rand_sym(10, 79)
+    for kind in (0, 1):
+        got = run_batch(hg, [small, A], [kind, kind])
+        assert got[1] == run_plain(hg, A, kind), (n, kind)
+        assert rel(got[0], oracle.brute(small, bool(kind)).value) < 1e-12
+    if n <= 34:
+        ref, kappa = oracle.formula(A, False, prec="dd", want_kappa=True)
+        assert ref.relerr(run_batch(hg, [A], [0])[0]) <= C_TOL * EPS * kappa
+
+
+def test_exact_counts(hg):
+    """0/1 graphs: perfect-matching counts are exact integers (small enough to be exact in double)."""
+    mats = [gi.random_graph(n, 0.5, 40 + n).astype(complex) for n in (8, 12, 16, 20, 24)]
+    got = run_batch(hg, mats, [0] * len(mats))
+    for A, g in zip(mats, got):
+        assert round(g.real) == oracle.brute_int(A.real.astype(np.int64)) and g.imag == 0
+
+
+def test_errors(hg):
+    import torch
+    from paper_1805_12498_amd._native import HafError
+    dA = torch.zeros(16, dtype=torch.complex128, device="cuda")
+    out = torch.zeros(2, dtype=torch.complex128, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    with pytest.raises(HafError, match="INVALID_ARG"):
+        hg.batched_dev(dA.data_ptr(), [0], [4], [2], out.data_ptr(), st)
+    with pytest.raises(HafError, match="INVALID_ARG"):
+        hg.batched_dev(dA.data_ptr(), [0], [-2], [0], out.data_ptr(), st)
+    with pytest.raises(HafError, match="TOO_LARGE"):
+        hg.batched_dev(dA.data_ptr(), [0], [66], [0], out.data_ptr(), st)
+    hg.batched_dev(dA.data_ptr(), [], [], [], out.data_ptr(), st)      # empty batch: nothing to do
+
+
+def test_autotuner(hg):
+    import torch
+    mats = gi.gbs_batch(64, seed=10)
+    flat, offs, sizes = gi.pack(mats)
+    kinds = np.ones(len(mats), dtype=np.uint8)
+    dA = torch.from_numpy(flat).cuda()
+    out = torch.zeros(len(mats), dtype=torch.complex128, device="cuda")
+    cfg, ms = hg.batched_tune(dA.data_ptr(), offs, sizes, kinds, out.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream)
+    print("tuned:", cfg, "%.3f ms" % ms, flush=True)
+    assert hg.batched_config() == cfg and ms > 0 and cfg["streams"] in (1, 2, 4, 8, 16)
+    tuned = out.cpu().numpy()
+    again = run_batch(hg, mats, kinds)
+    assert np.array_equal(tuned, again)
+    hg.set_batched_config(streams=8)
