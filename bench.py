@@ -1,4 +1,5 @@
-"""Benchmark: subset-terms/s of one 56x56 hafnian on one MI355X.
+"""Benchmark: subset-terms/s of one 56x56 hafnian on one MI355X, plus the
+batched and serving throughput against the plain one-hafnian-per-call path.
 
 A step is one complete hafnian of the 56x56 complex Gaussian symmetric matrix
 (seed 5601): all 2^28 subset terms (gather, Hessenberg reduction,
@@ -6,7 +7,17 @@ characteristic polynomial, power traces, series) and the signed double-double
 sum, with the matrix already resident in device memory.  The printed JSON line
 carries the throughput, the roofline position of the dominant kernel (the
 per-subset coefficient kernel, timed with HIP events on its own stream inside
-the timed region) and the CPU oracle timed on a bounded sample.
+the timed region), the CPU oracle timed on a bounded sample, and two extra
+objects measured after the timed steps:
+
+  batched  4096 GBS-style loop hafnians, n in [8, 32] (seed 4096), one batched
+           call (after the autotuner) versus 4096 single-matrix calls on one
+           stream; haf/s of each and whether every result agrees bitwise;
+  serving  a Poisson stream of haf / lhaf requests, n in [12, 44] with
+           geometric skew (seed 2027), replayed open-loop through the
+           continuous-batching server and through the plain server (one
+           request at a time), at a rate set from the plain server's measured
+           capacity; p50 / p99 latency (completion minus arrival) and haf/s.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 56] [--kind haf|lhaf]
 """
@@ -37,11 +48,11 @@ def cpu_baseline(A, n, loops, seconds_target=15.0):
     N = n // 2
     threads = os.cpu_count() or 1
     rng = np.random.default_rng(12345)
-    probe = rng.integers(1, 1 << N, size=8 * threads, dtype=np.int64).astype(np.uint32)
+    probe = rng.integers(1, 1 << N, size=64 * threads, dtype=np.int64).astype(np.uint32)
     t0 = time.time()
     oracle.formula_masks(A, probe, loops=loops, prec="ld", threads=threads)
     dt = max(time.time() - t0, 1e-3)
-    count = int(max(8 * threads, min(2_000_000, len(probe) * seconds_target / dt)))
+    count = int(max(64 * threads, min(4_000_000, len(probe) * seconds_target / dt)))
     masks = rng.integers(1, 1 << N, size=count, dtype=np.int64).astype(np.uint32)
     t0 = time.time()
     oracle.formula_masks(A, masks, loops=loops, prec="ld", threads=threads)
@@ -49,6 +60,96 @@ def cpu_baseline(A, n, loops, seconds_target=15.0):
     return {"value": count / dt, "unit": "subset-terms/s", "cores": threads, "kind": "oracle",
             "sample": "%d uniformly random subsets of the %dx%d matrix (%s), long double, %.1f s" % (
                 count, n, n, "lhaf" if loops else "haf", dt)}
+
+
+def bench_batched(hg, gi, count=4096):
+    """One batched call over the GBS-style batch versus the plain path, one call per matrix."""
+    import numpy as np
+    import torch
+
+    mats = gi.gbs_batch(count, seed=gi.SEED_BATCH)
+    flat, offs, sizes = gi.pack(mats)
+    kinds = np.ones(count, dtype=np.uint8)
+    dA = torch.from_numpy(flat).cuda()
+    out_b = torch.zeros(count, dtype=torch.complex128, device="cuda")
+    out_p = torch.zeros(count, dtype=torch.complex128, device="cuda")
+    stream = torch.cuda.current_stream()
+    cfg, tune_ms = hg.batched_tune(dA.data_ptr(), offs, sizes, kinds, out_b.data_ptr(), stream.cuda_stream)
+    log("batched autotuner:", cfg, "%.1f ms" % tune_ms)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hg.batched_dev(dA.data_ptr(), offs, sizes, kinds, out_b.data_ptr(), stream.cuda_stream)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    base = dA.data_ptr()
+    for t in range(min(count, 64)):       # warm the single-matrix path's workspaces
+        hg.haf_dev(base + 16 * int(offs[t]), int(sizes[t]), int(sizes[t]), out_p.data_ptr() + 16 * t,
+                   stream.cuda_stream, kind=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(count):
+        hg.haf_dev(base + 16 * int(offs[t]), int(sizes[t]), int(sizes[t]), out_p.data_ptr() + 16 * t,
+                   stream.cuda_stream, kind=1)
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t0
+    same = bool(torch.equal(torch.view_as_real(out_b), torch.view_as_real(out_p)))
+    terms = int(sum(1 << (int(n) // 2) for n in sizes))
+    return {"workload": "%d loop hafnians of GBS-style submatrices, n in [8, 32] (mean %.1f), seed %d"
+                        % (count, float(np.mean(sizes)), gi.SEED_BATCH),
+            "haf_per_s": count / t_b, "ms": t_b * 1e3, "subset_terms_per_s": terms / t_b,
+            "plain_haf_per_s": count / t_p, "plain_ms": t_p * 1e3, "speedup_vs_plain": t_p / t_b,
+            "bitwise_equal_to_plain": same, "tuned_config": cfg}
+
+
+def replay(hg, trace, t_offset, **cfg):
+    """Open-loop replay: submit each request at its arrival time; latency = done - arrival."""
+    import numpy as np
+
+    srv = hg.Server(**cfg)
+    try:
+        start = hg.now() + t_offset
+        arrival = {}
+        results = []
+        for t_arr, kind, A in trace:
+            target = start + t_arr
+            while True:
+                now = hg.now()
+                if now >= target:
+                    break
+                if target - now > 2e-3:
+                    time.sleep(min(target - now - 1e-3, 0.05))
+                results.extend(srv.poll(4096))
+            arrival[srv.submit(A, kind)] = target
+        srv.drain()
+        results.extend(srv.poll(len(trace) + 10))
+        end = hg.now()
+    finally:
+        srv.close()
+    lat = np.array([r.t_done - arrival[r.ticket] for r in results])
+    assert all(r.status == 0 for r in results) and len(results) == len(trace)
+    span = end - start
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "haf_per_s": len(trace) / span, "requests": len(trace),
+            "seconds": span}
+
+
+def bench_serving(hg, gi, seconds):
+    """Capacity of the plain server (closed loop), then an open-loop Poisson stream at half of it,
+    replayed through both servers."""
+    probe = gi.serving_trace(400, qps=1e9, seed=gi.SEED_SERVE + 1)
+    plain_cap = replay(hg, probe, 0.0, continuous=0)["haf_per_s"]
+    cont_cap = replay(hg, probe, 0.0, continuous=1)["haf_per_s"]
+    qps = 0.5 * plain_cap
+    num = max(200, int(qps * seconds))
+    trace = gi.serving_trace(num, qps=qps, seed=gi.SEED_SERVE)
+    cont = replay(hg, trace, 0.05, continuous=1)
+    plain = replay(hg, trace, 0.05, continuous=0)
+    log("serving: capacity plain %.0f, continuous %.0f req/s; at %.0f req/s p50/p99 %.2f/%.2f ms vs plain %.2f/%.2f ms"
+        % (plain_cap, cont_cap, qps, cont["p50_ms"], cont["p99_ms"], plain["p50_ms"], plain["p99_ms"]))
+    return {"workload": "Poisson arrivals, haf/lhaf 50/50, n = 12 + 2j with P(j) ~ 0.7^j up to 44, "
+                        "GBS-style submatrices, seed %d" % gi.SEED_SERVE,
+            "qps": qps, "continuous": cont, "plain": plain,
+            "capacity_haf_per_s": {"continuous": cont_cap, "plain": plain_cap}}
 
 
 def main():
@@ -61,6 +162,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--kernel-path", type=int, default=0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -139,6 +243,10 @@ def main():
         "fp64_model_tflops_step": prof["coef_model_flops"] / secs / 1e12,
         "cpu_baseline": None,
     }
+    if not args.no_batched:
+        line["batched"] = bench_batched(hg, gi)
+    if not args.no_serving:
+        line["serving"] = bench_serving(hg, gi, args.serve_seconds)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(A, n, kind == hg.KIND_LHAF, args.cpu_seconds)
         line["cpu_baseline"]["gpu_over_cpu"] = line["value"] / line["cpu_baseline"]["value"]

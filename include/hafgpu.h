@@ -196,32 +196,49 @@ int haf_profile_enable(int on);
 int haf_profile_read(haf_profile* out);
 
 /* ------------------------------------------------------------------------ */
-/* Serving: a continuous-batching request server.                            */
+/* Serving: a continuous-batching request server.
+ *
+ * submit() validates the matrix (as the host entry points do), copies it and
+ * queues it; it never waits for the device.  The server's scheduler thread
+ * admits queued requests in arrival order whenever a request slot is free and
+ * the device arena holds room for the request's state (its matrix and its
+ * result), and enqueues each admitted request at once on the least-loaded of
+ * its streams, so that requests admitted while others run overlap with them
+ * on the device.  A result is bitwise the single-matrix path's result for that
+ * matrix, whatever else the server runs.  Results are collected with poll().
+ * The per-stream work buffers of the hafnian computation are the library's
+ * usual workspaces and are not counted in arena_bytes.                       */
 typedef struct haf_server haf_server;
 
 typedef struct {
     int device;                 /* HIP device ordinal                                  */
-    int64_t arena_bytes;        /* device bytes for admitted requests (matrices + state) */
+    int64_t arena_bytes;        /* device bytes for admitted requests: n^2 * 16 rounded
+                                   up to 256, plus 256, per request                     */
     int max_active;             /* request slots on the device                          */
     int max_queue;              /* host queue length before submit returns HAF_E_BUSY   */
-    int tick_units;             /* work units (subset chunks) launched per step         */
-    int continuous;             /* 1: admit between steps (continuous batching);
-                                   0: one request at a time, FIFO (the plain server)    */
+    int streams;                /* streams the admitted requests are spread over        */
+    int continuous;             /* 1: admit whenever there is room (continuous batching);
+                                   0: one request at a time on one stream, in arrival
+                                   order (the plain server)                             */
 } haf_server_config;
 
 typedef struct {
     uint64_t ticket;
-    int status;                 /* HAF_OK or an error code                              */
+    int status;                 /* HAF_OK, HAF_E_DEVICE, or HAF_E_STATE if the server
+                                   stopped before admitting the request                 */
     int n, kind;
     haf_cplx value;
-    double t_submit, t_admit, t_done;   /* seconds on the host steady clock           */
+    double t_submit, t_admit, t_done;   /* seconds on the host steady clock (haf_now) */
 } haf_result;
 
-/* Fill *cfg with defaults. */
+/* Fill *cfg with defaults (1 GiB arena, 256 slots, 8 streams, continuous). */
 void haf_server_default_config(haf_server_config* cfg);
-/* Start a server (its scheduler thread owns one HIP stream). NULL on failure. */
+/* Start a server: allocates the arena and starts its scheduler thread.  NULL
+ * on failure (haf_last_error() says why). */
 haf_server* haf_server_create(const haf_server_config* cfg);
-/* Copy the host matrix A and queue it; non-blocking.  *ticket identifies it. */
+/* Copy the host matrix A and queue it; non-blocking.  *ticket identifies it.
+ * Errors as for haf_c128, plus HAF_E_BUSY (queue full), HAF_E_NOMEM (the
+ * request alone is larger than the arena), HAF_E_STATE (server stopping). */
 int haf_server_submit(haf_server* s, const haf_cplx* A, int n, int lda, int kind, uint64_t* ticket);
 /* Move up to max finished results into out; *n_out tells how many. */
 int haf_server_poll(haf_server* s, haf_result* out, int max, int* n_out);

@@ -49,7 +49,7 @@ class c128x2(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("arena_bytes", ctypes.c_int64), ("max_active", ctypes.c_int),
-                ("max_queue", ctypes.c_int), ("tick_units", ctypes.c_int), ("continuous", ctypes.c_int)]
+                ("max_queue", ctypes.c_int), ("streams", ctypes.c_int), ("continuous", ctypes.c_int)]
 
 
 class Profile(ctypes.Structure):
