@@ -34,6 +34,26 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6          # MI355X vector FP64: 256 CU x 128 flop/clk x 2.4 GHz
 
+# HBM bytes per launch of the coefficient kernel at n = 56 (haf), from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs calibrated against a 1 GiB copy
+# (profiles/coef_kernel_n56_haf_hbm_traffic.md), valid only while the kernel's
+# sources are the ones those counters were taken on.
+TRAFFIC_SOURCES = ("paper_1805_12498_amd/csrc/haf_coef_reg.hpp", "paper_1805_12498_amd/csrc/haf_kernels_reg.hip",
+                   "paper_1805_12498_amd/csrc/haf_common.hpp")
+TRAFFIC_SHA256 = "cd9093fde1567c22f75b3e2793d3184cd8c8a36e85b48305da0c1cfa0853eade"
+TRAFFIC_N56_HAF_BYTES_PER_LAUNCH = 8.879e8
+
+
+def coef_traffic(n, kind):
+    import hashlib
+    if n != 56 or kind != "haf":
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_N56_HAF_BYTES_PER_LAUNCH if h.hexdigest() == TRAFFIC_SHA256 else None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -233,7 +253,8 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None,
+            "traffic": coef_traffic(n, args.kind),
+            "traffic_unit": "bytes per launch",
             "kernel": "coefficient kernel (per-subset Hessenberg + characteristic polynomial)",
             "model": "(44/3) s^3 flops per subset of size s (+ 8 (N-1) s^2 for loop hafnians)",
             "launches": prof["coef_launches"],
