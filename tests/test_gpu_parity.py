@@ -253,3 +253,80 @@ def test_terms_vs_oracle_terms(hg):
         for i, m in enumerate(masks):
             ref = oracle.term(A, int(m), bool(kind), prec="dd").value
             assert rel(got[i], ref) < 1e-11, (kind, int(m), got[i], ref)
+
+
+# ---------------------------------------------------------------- the 56x56 workloads
+def kappa_from_oracle_sample(A, loops, value, samples, seed):
+    """kappa = sum_Z |f(Z)| / |haf| with sum_Z |f(Z)| estimated from the oracle's own terms
+    (double-double) on a uniform sample of nonempty subsets."""
+    N = A.shape[0] // 2
+    rng = np.random.default_rng(seed)
+    masks = rng.integers(1, 1 << N, size=samples, dtype=np.int64)
+    mean = np.mean([abs(oracle.term(A, int(m), loops, prec="dd").value) for m in masks])
+    return mean * ((1 << N) - 1) / abs(value)
+
+
+def test_n56_bipartite_vs_ryser(hg):
+    """haf([[0, W], [W^T, 0]]) = per(W) (Sec. 1.1, Eq. bipartite), W 28x28 Gaussian (seed 5603):
+    the full 2^28-term sum against the double-double Ryser permanent."""
+    W = gi.gaussian_square(28, gi.SEED_N56_BIPARTITE)
+    A = gi.bipartite_embed(W)
+    ref = gold_value("n56_bipartite")
+    got = hg.haf_host(A, 0)
+    err = ref.relerr(got)
+    kappa = kappa_from_oracle_sample(A, False, ref.value, 400, 1)
+    record("n=56 bipartite seed 5603 (Ryser)", err, kappa)
+    # the sampled kappa is an estimate: a factor 4 of slack on top of the usual 64
+    assert err <= 4 * C_TOL * EPS * kappa, (err, kappa)
+
+
+def test_n56_sampled_terms_vs_oracle(hg):
+    """f(Z) of the 56x56 Gaussian matrix (seed 5601) for subsets of every size class, against the
+    oracle's explicit-power terms in double-double."""
+    import torch
+    n = 56
+    A = gi.gaussian_symmetric(n, gi.SEED_N56)
+    rng = np.random.default_rng(56)
+    masks = [(1 << 28) - 1]
+    for m in (1, 2, 5, 9, 14, 18, 22, 26, 27):
+        for _ in range(3):
+            masks.append(int(sum(1 << int(b) for b in rng.choice(28, m, replace=False))))
+    masks = np.array(sorted(set(masks)), dtype=np.uint32)
+    dA = torch.from_numpy(A).cuda()
+    dm = torch.from_numpy(masks.astype(np.int32)).cuda()
+    dt = torch.zeros(len(masks), dtype=torch.complex128, device="cuda")
+    hg.terms_dev(dA.data_ptr(), n, n, 0, dm.data_ptr(), len(masks), dt.data_ptr(), 0)
+    torch.cuda.synchronize()
+    got = dt.cpu().numpy()
+    worst = 0.0
+    for g, m in zip(got, masks):
+        ref = oracle.term(A, int(m), False, prec="dd")
+        e = ref.relerr(g)
+        worst = max(worst, e)
+        assert e < 1e-9, (bin(int(m)).count("1"), e)
+    record("n=56 sampled terms, worst", worst, 1.0)
+
+
+def test_n56_graph_sampled_terms_exact(hg):
+    """The 56-vertex 0/1 graph (edge probability 1/2, seed 5602): each f(Z) counts tangles
+    (Sec. 3.2), an integer, computed exactly by the oracle modulo six primes and
+    reconstructed by CRT (checked with a seventh); the GPU's FP64 terms must round to it."""
+    import torch
+    n = 56
+    G = gi.random_graph(n, 0.5, gi.SEED_N56_GRAPH)
+    rng = np.random.default_rng(5602)
+    masks = [(1 << 28) - 1] + [int(sum(1 << int(b) for b in rng.choice(28, m, replace=False)))
+                               for m in (3, 8, 13, 17, 21, 25)]
+    masks = np.array(masks, dtype=np.uint32)
+    dA = torch.from_numpy(G.astype(complex)).cuda()
+    dm = torch.from_numpy(masks.astype(np.int32)).cuda()
+    dt = torch.zeros(len(masks), dtype=torch.complex128, device="cuda")
+    hg.terms_dev(dA.data_ptr(), n, n, 0, dm.data_ptr(), len(masks), dt.data_ptr(), 0)
+    torch.cuda.synchronize()
+    got = dt.cpu().numpy()
+    for g, m in zip(got, masks):
+        res = [oracle.modp_term(G, int(m), p) for p in oracle.PRIMES[:7]]
+        exact, M = oracle.crt(res[:6], oracle.PRIMES[:6])
+        assert exact % oracle.PRIMES[6] == res[6]
+        assert exact >= 0
+        assert abs(g.real - exact) <= 1e-11 * exact + 0.5 and abs(g.imag) <= 1e-11 * exact + 0.5, (m, g, exact)
