@@ -167,9 +167,11 @@ int haf_batched_plan(const int32_t* h_n, const uint8_t* h_kind, int count, int32
 int haf_release_workspaces(void);
 
 /* Kernel path selection (for testing and tuning): 0 = automatic, 1 = LDS
- * kernel only, 2 = register-tiled kernels with the default layout table,
- * 3 = register-tiled kernels with one full wave per matrix above s = 16.
- * Process-wide. */
+ * kernel only (Householder), 2 = register-tiled kernels with Householder
+ * reflections, 3 = as 2 with one full wave per matrix above s = 16,
+ * 4 = register-tiled kernels with the Hessenberg form by elimination with row
+ * and column exchanges.  All reach the same characteristic polynomial (any
+ * similarity does, App. B); they differ in rounding.  Process-wide. */
 int haf_set_kernel_path(int path);
 
 /* ------------------------------------------------------------------------ */

@@ -114,6 +114,18 @@ __device__ __forceinline__ double group_sum(double x) {
     return x;
 }
 
+// Maximum over aligned groups of L lanes (same exchange pattern as group_sum).
+template <int L>
+__device__ __forceinline__ double group_max(double x) {
+    x = fmax(x, dpp_d<0xB1>(x));
+    x = fmax(x, dpp_d<0x4E>(x));
+    if (L >= 8) x = fmax(x, dpp_d<0x141>(x));
+    if (L >= 16) x = fmax(x, dpp_d<0x140>(x));
+    if (L >= 32) x = fmax(x, swizzle_d<0x401F>(x));
+    if (L >= 64) x = fmax(x, xor32_d(x));
+    return x;
+}
+
 // ---------------------------------------------------------------- double-double
 struct dd { double hi, lo; };
 __device__ __forceinline__ dd dd_two_sum(double a, double b) {

@@ -15,10 +15,12 @@ hipError_t launch_coef_lds(int smax, bool loops, int grid, hipStream_t st, const
                            int64_t cstride);
 
 // Register-tiled coefficient kernel for subsets of s <= reg_max_s() rows (same
-// outputs).  grid_waves bounds the number of one-wave workgroups.
+// outputs).  grid_waves bounds the number of one-wave workgroups.  elim selects
+// the Hessenberg reduction by elimination with exchanges (default layouts only),
+// otherwise Householder reflections (wide: one wave per matrix above s = 16).
 hipError_t launch_coef_reg(int s, bool loops, int grid_waves, hipStream_t st, const double2* A, int lda, int N,
                            int m, uint64_t rank0, int count, const uint32_t* masks, const int* d_exp,
-                           double2* coef, int64_t cstride, bool wide);
+                           double2* coef, int64_t cstride, bool wide, bool elim);
 int reg_max_s();
 
 // Exponent e of the exact input scaling (off-diagonal by 2^-2e, diagonal by

@@ -30,8 +30,11 @@ GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_
 def hg():
     import paper_1805_12498_amd as hg
     hg.load()
+    # HAFGPU_KERNEL_PATH runs the whole suite on one kernel path (see haf_set_kernel_path)
+    hg.set_kernel_path(int(os.environ.get("HAFGPU_KERNEL_PATH", "0")))
     print("device:", hg.device_info(), flush=True)
-    return hg
+    yield hg
+    hg.set_kernel_path(0)
 
 
 _RECORDS = []
