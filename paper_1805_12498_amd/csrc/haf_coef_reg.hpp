@@ -397,17 +397,22 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             const double2 alpha = colb[j + 1];
             const double sig = group_sum<L>(lam >= j + 2 ? fma(x.x, x.x, x.y * x.y) : 0.0);
             const double tot = fma(alpha.x, alpha.x, fma(alpha.y, alpha.y, sig));
-            // inputs are pre-scaled to entries of order one, so a column this small is
-            // rounding noise of an already reduced (rank-deficient) part: leave it
-            const bool skip = tot < 0x1p-960 || (sig == 0.0 && alpha.y == 0.0);
-            double2 tau = cz(), scal = cz(), v = cz();
+            // inputs are pre-scaled to entries of order one, so a column whose squared norm is
+            // below 2^-660 is rounding noise of an already reduced (rank-deficient) part:
+            // leave it (the bound also keeps 1 / (beta |alpha - beta|^2) below 2^990)
+            const bool skip = tot < 0x1p-660 || (sig == 0.0 && alpha.y == 0.0);
+            double2 tau = cz(), v = cz();
             double bet = alpha.x;
             if (!skip) {
+                // reflector P = I - tau v v^H with v unnormalised: v_{j+1} = d = alpha - beta,
+                // v_r = x_r below it, tau = -1 / (beta conj(d)) = -d / (beta |d|^2); the same P
+                // as v_{j+1} = 1, tau = (beta - alpha) / beta, for one division instead of three
                 const double nrm = sqrt(tot);
                 bet = alpha.x >= 0.0 ? -nrm : nrm;
-                tau = make_double2((bet - alpha.x) / bet, -alpha.y / bet);
-                scal = crecip(make_double2(alpha.x - bet, alpha.y));
-                v = lam == j + 1 ? cone() : (lam > j + 1 ? cmul(x, scal) : cz());
+                const double2 d = make_double2(alpha.x - bet, alpha.y);
+                const double rb = -1.0 / (bet * fma(d.x, d.x, d.y * d.y));
+                tau = cscale(d, rb);
+                v = lam == j + 1 ? d : (lam > j + 1 ? x : cz());
             }
             if (lam < SM) vv[lam] = v;
             if (lam == 0) beta[j + 1] = skip ? alpha : make_double2(bet, 0.0);
@@ -510,13 +515,19 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             }
         __syncthreads();
         for (int z = lam; z < S::SLACK; z += L) red[s * (s + 1) / 2 + z] = cz();   // slack after the table
-        // g_{r,c+1} = h_{r,c} prod_{k=r+1}^{c} h_{k,k-1}: lane r walks its row
-        if (lam < s) {
+        // g_{r,c+1} = h_{r,c} prod_{k=r+1}^{c} h_{k,k-1}: lane r walks its row; the
+        // trip count is the same for every lane (lanes join at c = r), so the loop
+        // unrolls and the reads of the next subdiagonal entries are issued early
+        {
             double2 pi = cone();
-            for (int c = lam; c < s; ++c) {
-                const int idx = c * (c + 1) / 2 + lam;
-                red[idx] = cmul(red[idx], pi);
-                if (c + 1 < s) pi = cmul(pi, beta[c + 1]);
+#pragma unroll 4
+            for (int c = 0; c < s; ++c) {
+                const double2 bc = beta[c + 1 < s ? c + 1 : 0];
+                if (c >= lam && lam < s) {
+                    const int idx = c * (c + 1) / 2 + lam;
+                    red[idx] = cmul(red[idx], pi);
+                    pi = cmul(pi, bc);
+                }
             }
         }
         __syncthreads();
