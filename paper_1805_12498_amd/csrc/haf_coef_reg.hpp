@@ -41,7 +41,7 @@ struct RegShape {
     static constexpr int W = 64 / L;                       // matrices per wave
     static constexpr int SM = (P * R < Q * C) ? P * R : Q * C;   // largest s
     static constexpr int RED = L * (R + C);                // transposition area (w and y partials)
-    static constexpr int VEC = 4 * SM + SM / 2;            // column, v, w', y1 + vertex ids
+    static constexpr int VEC = 4 * SM + SM / 2;            // column, v, w', y1 (+ spare)
     static constexpr int GN = SM * (SM + 1) / 2;           // packed upper triangle
     static constexpr int SLACK = 8 * W;                    // zeroed, read past the table in whole chunks
     // during the reduction the area holds the partials and the vectors; afterwards
@@ -57,6 +57,54 @@ struct RegShape {
 __device__ __forceinline__ uint32_t next_subset(uint32_t x) {
     const uint32_t r = x + (x & (0u - x));
     return (((r ^ x) >> 2) >> __builtin_ctz(x)) | r;
+}
+
+// Mask of the q-th subset of a run starting at rank `first` (in masks[], or by
+// unranking rank0 + first and Gosper steps from `prev`); past the end of the
+// chunk any m-subset stands in (computed, never written).
+__device__ __forceinline__ uint32_t run_subset_mask(int q, uint32_t prev, int first, int count,
+                                                    const uint32_t* __restrict__ masks, uint64_t rank0, int m, int N) {
+    const int sub = first + q;
+    const bool valid = sub < count;
+    uint32_t mk;
+    if (masks) mk = masks[valid ? sub : 0];
+    else mk = q == 0 ? unrank_subset(rank0 + (uint64_t)(valid ? sub : 0), m, N) : next_subset(prev);
+    return valid ? mk : (1u << m) - 1u;
+}
+
+// Lane (a, b)'s tile of B = X A_off on the subset: row r of B is row v(r)^1 of
+// A and column c is column v(c), v(r) = member r&1 of the (r/2)-th chosen pair.
+// The lane's rows a + P t are found by stepping over P/2 pairs at a time (P and
+// Q are even, so the member bit is a&1 for all of them; likewise for columns).
+template <int P, int Q, int R, int C>
+__device__ __forceinline__ void gather_tile(double2 (&hh)[R][C], uint32_t mk, int a, int b, int s,
+                                            const double2* __restrict__ A, int lda, double off_scale) {
+    int rv[R], cv[C];
+    uint32_t mm = mk;
+    for (int z = 0; z < (a >> 1); ++z) mm &= mm - 1u;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        rv[t] = (a + P * t < s) ? 2 * __builtin_ctz(mm) + (a & 1) : 0;
+#pragma unroll
+        for (int z = 0; z < P / 2; ++z) mm &= mm - 1u;
+    }
+    mm = mk;
+    for (int z = 0; z < (b >> 1); ++z) mm &= mm - 1u;
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+        cv[u] = (b + Q * u < s) ? 2 * __builtin_ctz(mm) + (b & 1) : 0;
+#pragma unroll
+        for (int z = 0; z < Q / 2; ++z) mm &= mm - 1u;
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const double2* arow = A + (int64_t)(rv[t] ^ 1) * lda;
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+            const int r = a + P * t, c = b + Q * u;
+            hh[t][u] = (r < s && c < s && c != (r ^ 1)) ? cscale(arow[cv[u]], off_scale) : cz();
+        }
+    }
 }
 
 // Characteristic polynomials of the leading principal blocks of the Hessenberg
@@ -162,7 +210,6 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
     double2* vv = colb + SM;                  // Householder vector v
     double2* wb = vv + SM;                    // w' = conj(tau) v^H H
     double2* yb = wb + SM;                    // y1 = tau (H v - conj(tau) gamma v)
-    int* vid = (int*)(yb + SM);               // subset vertex of each row (SM ints)
     double2* beta = red + S::AREA;            // subdiagonal of the Hessenberg form
     double2* wpart = red;                     // [lane][u]
     double2* ypart = red + L * C;             // [lane][t]
@@ -174,40 +221,21 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
     for (int q = 0; q < span; ++q) {
         const int sub = first + q;
         const bool valid = sub < count;
-        if (masks) mask = masks[valid ? sub : 0];
-        else mask = q == 0 ? unrank_subset(rank0 + (uint64_t)(valid ? sub : 0), m, N) : next_subset(mask);
-        if (!valid) mask = (1u << m) - 1u;    // any m-subset: computed, never written
-
-        // ---- vertex of each row: row r is member r&1 of the (r/2)-th chosen pair
-        if (lam < s) vid[lam] = subset_vertex(mask, lam);
-        __syncthreads();
-        int rv[R], cv[C];
-#pragma unroll
-        for (int t = 0; t < R; ++t) rv[t] = (a + P * t < s) ? vid[a + P * t] : 0;
-#pragma unroll
-        for (int u = 0; u < C; ++u) cv[u] = (b + Q * u < s) ? vid[b + Q * u] : 0;
-
-        // ---- gather the tile of B = X A_off on Z (row r of B is row vid[r]^1 of A)
+        mask = run_subset_mask(q, mask, first, count, masks, rank0, m, N);
         double2 h[R][C];
-#pragma unroll
-        for (int t = 0; t < R; ++t) {
-            const double2* arow = A + (int64_t)(rv[t] ^ 1) * lda;
-#pragma unroll
-            for (int u = 0; u < C; ++u) {
-                const int r = a + P * t, c = b + Q * u;
-                h[t][u] = (r < s && c < s && c != (r ^ 1)) ? cscale(arow[cv[u]], off_scale) : cz();
-            }
-        }
+        gather_tile<P, Q, R, C>(h, mask, a, b, s, A, lda, off_scale);
 
         // ---- loop moments l_k = d^T B^(k-1) X d  (lane lam owns index lam of d)
         if (LOOPS) {
-            const int vl = lam < s ? vid[lam] : 0;
+            const int vl = lam < s ? subset_vertex(mask, lam) : 0;
             const double2 dl = lam < s ? cscale(A[(int64_t)vl * lda + vl], diag_scale) : cz();
             const double2 dp = lam < s ? cscale(A[(int64_t)(vl ^ 1) * lda + (vl ^ 1)], diag_scale) : cz();
             double2 yc[C];                     // y at own columns; y_0 = X d, (X d)_c = d_{c^1}
 #pragma unroll
-            for (int u = 0; u < C; ++u)
-                yc[u] = (b + Q * u < s) ? cscale(A[(int64_t)(cv[u] ^ 1) * lda + (cv[u] ^ 1)], diag_scale) : cz();
+            for (int u = 0; u < C; ++u) {
+                const int vc = (b + Q * u < s) ? subset_vertex(mask, b + Q * u) ^ 1 : 0;
+                yc[u] = (b + Q * u < s) ? cscale(A[(int64_t)vc * lda + vc], diag_scale) : cz();
+            }
             double2 prod = cmul(dl, dp);
             double lx = group_sum<L>(prod.x), ly = group_sum<L>(prod.y);
             if (valid && lam == 0) coef[(int64_t)N * cstride + sub] = make_double2(lx, ly);
