@@ -40,7 +40,13 @@ struct RegShape {
     static constexpr int L = P * Q;                        // lanes per matrix
     static constexpr int W = 64 / L;                       // matrices per wave
     static constexpr int SM = (P * R < Q * C) ? P * R : Q * C;   // largest s
-    static constexpr int RED = L * (R + C);                // transposition area (w and y partials)
+    // transposition area: the w partial of column c from row group a sits at
+    // c + WA * a, the y partial of row r from column group b at r + YB * b.  The pads
+    // make both the stores (lane = (a, b)) and the sums (lane = column or row) hit
+    // distinct LDS banks in every run of 8 or 16 lanes.
+    static constexpr int WA = Q * C + ((C % 2 == 0) ? Q : 0);
+    static constexpr int YB = P * R + (Q >= 8 ? 1 : 2);
+    static constexpr int RED = P * WA + Q * YB;
     static constexpr int VEC = 4 * SM + SM / 2;            // column, v, w', y1 (+ spare)
     static constexpr int GN = SM * (SM + 1) / 2;           // packed upper triangle
     static constexpr int SLACK = 8 * W;                    // zeroed, read past the table in whole chunks
@@ -211,8 +217,8 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
     double2* wb = vv + SM;                    // w' = conj(tau) v^H H
     double2* yb = wb + SM;                    // y1 = tau (H v - conj(tau) gamma v)
     double2* beta = red + S::AREA;            // subdiagonal of the Hessenberg form
-    double2* wpart = red;                     // [lane][u]
-    double2* ypart = red + L * C;             // [lane][t]
+    double2* wpart = red;                     // [a][column], row stride WA
+    double2* ypart = red + P * S::WA;         // [b][row], stride YB
     const int s = 2 * m;
 
     // tid = lane in the wave; group g of the wave owns the run of `span` subsets starting at (grp0 + g) * span
@@ -245,15 +251,14 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                     double2 acc = cz();
 #pragma unroll
                     for (int u = 0; u < C; ++u) cfma(acc, h[t][u], yc[u]);
-                    ypart[lam * R + t] = acc;
+                    ypart[a + P * t + S::YB * b] = acc;
                 }
                 __syncthreads();
                 double2 yr = cz();            // (B y)_lam
                 if (lam < s) {
-                    const int ra = lam % P, rt = lam / P;
 #pragma unroll
                     for (int bb = 0; bb < Q; ++bb) {
-                        const double2 pp = ypart[(ra * Q + bb) * R + rt];
+                        const double2 pp = ypart[lam + S::YB * bb];
                         yr.x += pp.x;
                         yr.y += pp.y;
                     }
@@ -389,7 +394,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                 }
 #undef HAF_PI
 #pragma unroll
-            for (int t = 0; t < R; ++t) ypart[lam * R + t] = yp[t];
+            for (int t = 0; t < R; ++t) ypart[a + P * t + S::YB * b] = yp[t];
             __syncthreads();
             const int un = (j + 1) / Q, bn = (j + 1) % Q;
             if (b == bn) {
@@ -401,7 +406,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                             double2 y = cz();
 #pragma unroll
                             for (int bb = 0; bb < Q; ++bb) {
-                                const double2 pp = ypart[(a * Q + bb) * R + t];
+                                const double2 pp = ypart[a + P * t + S::YB * bb];
                                 y.x += pp.x;
                                 y.y += pp.y;
                             }
@@ -464,27 +469,25 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                         cfma_cj(wp, vr[t], h[t][u]);
                         cfma(yp[t], h[t][u], vcu);
                     }
-                    wpart[lam * C + u] = wp;
+                    wpart[b + Q * u + S::WA * a] = wp;
                 }
 #pragma unroll
-            for (int t = 0; t < R; ++t) ypart[lam * R + t] = yp[t];
+            for (int t = 0; t < R; ++t) ypart[a + P * t + S::YB * b] = yp[t];
             __syncthreads();
             // lane lam owns column lam (w) and row lam (y)
             double2 w = cz(), y = cz();
             if (lam > j && lam < s) {
-                const int cb = lam % Q, cu = lam / Q;
 #pragma unroll
                 for (int aa = 0; aa < P; ++aa) {
-                    const double2 pp = wpart[(aa * Q + cb) * C + cu];
+                    const double2 pp = wpart[lam + S::WA * aa];
                     w.x += pp.x;
                     w.y += pp.y;
                 }
             }
             if (lam < s) {
-                const int ra = lam % P, rt = lam / P;
 #pragma unroll
                 for (int bb = 0; bb < Q; ++bb) {
-                    const double2 pp = ypart[(ra * Q + bb) * R + rt];
+                    const double2 pp = ypart[lam + S::YB * bb];
                     y.x += pp.x;
                     y.y += pp.y;
                 }
