@@ -440,10 +440,10 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                 // reflector P = I - tau v v^H with v unnormalised: v_{j+1} = d = alpha - beta,
                 // v_r = x_r below it, tau = -1 / (beta conj(d)) = -d / (beta |d|^2); the same P
                 // as v_{j+1} = 1, tau = (beta - alpha) / beta, for one division instead of three
-                const double nrm = sqrt(tot);
+                const double nrm = sqrt_pos(tot);
                 bet = alpha.x >= 0.0 ? -nrm : nrm;
                 const double2 d = make_double2(alpha.x - bet, alpha.y);
-                const double rb = -1.0 / (bet * fma(d.x, d.x, d.y * d.y));
+                const double rb = -rcp_normal(bet * fma(d.x, d.x, d.y * d.y));
                 tau = cscale(d, rb);
                 v = lam == j + 1 ? d : (lam > j + 1 ? x : cz());
             }

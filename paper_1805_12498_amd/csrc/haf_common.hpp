@@ -79,10 +79,11 @@ __device__ __forceinline__ double wave_max(double x) {
 constexpr double kTinyColumn = 0x1p-960;
 
 // ---------------------------------------------------------------- DPP / swizzle moves of a double
+// (a lane whose source is outside the wave reads 0; no register has to be zeroed first)
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 template <int PATTERN>
@@ -101,6 +102,14 @@ __device__ __forceinline__ double xor32_d(double x) {
     return __hiloint2double(upper ? h[0] : h[1], upper ? l[0] : l[1]);
 }
 
+// x(lanes 0..31) + x(lanes 32..63) for a value that is uniform within each half:
+// the swap hands every lane both halves, and every lane adds them in the same order
+__device__ __forceinline__ double halves_sum(double x) {
+    const auto l = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(x), false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(x), false, false);
+    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+}
+
 // Sum over aligned groups of L lanes (L = 4, 8, 16, 32, 64); every lane of a
 // group gets bitwise the same total (each stage adds the same two values).
 template <int L>
@@ -110,8 +119,26 @@ __device__ __forceinline__ double group_sum(double x) {
     if (L >= 8) x += dpp_d<0x141>(x);       // row_half_mirror: the other quad of the 8-group
     if (L >= 16) x += dpp_d<0x140>(x);      // row_mirror: the other 8-group of the row
     if (L >= 32) x += swizzle_d<0x401F>(x); // lane ^ 16 within 32
-    if (L >= 64) x += xor32_d(x);           // lane ^ 32
+    if (L >= 64) x = halves_sum(x);         // + lane ^ 32
     return x;
+}
+
+// sqrt(x) for normal x > 0: the hardware reciprocal square root refined by one
+// Goldschmidt step and a final Newton correction (within an ulp or two)
+__device__ __forceinline__ double sqrt_pos(double x) {
+    const double r = __builtin_amdgcn_rsq(x);
+    double g = x * r, h = 0.5 * r;
+    const double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    return fma(fma(-g, g, x), h, g);
+}
+// 1 / x for normal x whose reciprocal is normal: the hardware reciprocal and two
+// Newton steps (within an ulp)
+__device__ __forceinline__ double rcp_normal(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
 }
 
 // Maximum over aligned groups of L lanes (same exchange pattern as group_sum).
