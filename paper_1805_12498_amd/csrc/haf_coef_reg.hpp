@@ -47,7 +47,7 @@ struct RegShape {
     static constexpr int WA = Q * C + ((C % 2 == 0) ? Q : 0);
     static constexpr int YB = P * R + (Q >= 8 ? 1 : 2);
     static constexpr int RED = P * WA + Q * YB;
-    static constexpr int VEC = 4 * SM + SM / 2;            // column, v, w', y1 (+ spare)
+    static constexpr int VEC = 4 * SM + SM / 2;            // column, v, w', y1, row-group norms
     static constexpr int GN = SM * (SM + 1) / 2;           // packed upper triangle
     static constexpr int SLACK = 8 * W;                    // zeroed, read past the table in whole chunks
     // during the reduction the area holds the partials and the vectors; afterwards
@@ -56,7 +56,27 @@ struct RegShape {
     static constexpr int PER = AREA + SM;                  // + subdiagonal
     static_assert(L * W == 64, "group size must divide 64");
     static_assert(SM <= L, "the polynomial stage needs one lane per degree");
+    static_assert((P & (P - 1)) == 0 && (Q & (Q - 1)) == 0 && P <= SM, "tree sums over P and Q; P norms fit the spare");
 };
+
+// Sum of K values at p[0], p[D], ..., p[(K-1) D] by a fixed pairwise tree
+// (K a power of two): the same rounding as any lane doing the same sum, and a
+// dependency chain of log2 K additions instead of K.
+template <int K, int D>
+__device__ __forceinline__ double2 tree_sum(const double2* __restrict__ p) {
+    if constexpr (K == 1) {
+        return p[0];
+    } else {
+        const double2 l = tree_sum<K / 2, D>(p), r = tree_sum<K / 2, D>(p + (K / 2) * D);
+        return make_double2(l.x + r.x, l.y + r.y);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ double tree_sum_d(const double* __restrict__ p) {
+    if constexpr (K == 1) return p[0];
+    else return tree_sum_d<K / 2>(p) + tree_sum_d<K / 2>(p + K / 2);
+}
 
 // Next subset of the same size in increasing mask order (= the next rank of the
 // combinatorial number system), by Gosper's bit trick.
@@ -153,7 +173,7 @@ __device__ __forceinline__ double2 charpoly_lanes(const double2* __restrict__ gt
         }
         double2 tot = cadd(acc[0], acc[1]);
         if (SPLIT >= 4) { tot.x += swizzle_d<0x401F>(tot.x); tot.y += swizzle_d<0x401F>(tot.y); }   // lane ^ 16
-        if (SPLIT >= 2) { tot.x += xor32_d(tot.x); tot.y += xor32_d(tot.y); }                   // lane ^ 32
+        if (SPLIT >= 2) { tot.x = halves_sum(tot.x); tot.y = halves_sum(tot.y); }               // + lane ^ 32
         double2 sh;
         sh.x = dpp_d<0x138>(prev.x);          // wave_shr:1 -> c_{i-1}[d-1]
         sh.y = dpp_d<0x138>(prev.y);
@@ -216,6 +236,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
     double2* vv = colb + SM;                  // Householder vector v
     double2* wb = vv + SM;                    // w' = conj(tau) v^H H
     double2* yb = wb + SM;                    // y1 = tau (H v - conj(tau) gamma v)
+    double* nrmp = (double*)(yb + SM);        // per row group: squared norm of the next column below its subdiagonal
     double2* beta = red + S::AREA;            // subdiagonal of the Hessenberg form
     double2* wpart = red;                     // [a][column], row stride WA
     double2* ypart = red + P * S::WA;         // [b][row], stride YB
@@ -255,14 +276,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                 }
                 __syncthreads();
                 double2 yr = cz();            // (B y)_lam
-                if (lam < s) {
-#pragma unroll
-                    for (int bb = 0; bb < Q; ++bb) {
-                        const double2 pp = ypart[lam + S::YB * bb];
-                        yr.x += pp.x;
-                        yr.y += pp.y;
-                    }
-                }
+                if (lam < s) yr = tree_sum<Q, S::YB>(ypart + lam);
                 prod = cmul(dl, yr);
                 lx = group_sum<L>(prod.x);
                 ly = group_sum<L>(prod.y);
@@ -419,16 +433,21 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
 
         } else {
         // ---- Householder reduction to upper Hessenberg form
-        if (b == 0) {                          // column 0 -> colb
+        if (b == 0) {                          // column 0 -> colb, its norm below row 1 -> nrmp
+            double part = 0.0;
 #pragma unroll
-            for (int t = 0; t < R; ++t)
+            for (int t = 0; t < R; ++t) {
                 if (a + P * t < SM) colb[a + P * t] = h[t][0];
+                if (a + P * t >= 2) part = fma(h[t][0].x, h[t][0].x, fma(h[t][0].y, h[t][0].y, part));
+            }
+            nrmp[a] = part;
         }
         for (int j = 0; j + 2 < s; ++j) {
-            __syncthreads();                  // column j is in colb
+            __syncthreads();                  // column j is in colb, its row-group norms in nrmp
             const double2 x = (lam > j && lam < s) ? colb[lam] : cz();
             const double2 alpha = colb[j + 1];
-            const double sig = group_sum<L>(lam >= j + 2 ? fma(x.x, x.x, x.y * x.y) : 0.0);
+            // squared norm below the subdiagonal; rows past s are zero in the tile
+            const double sig = tree_sum_d<P>(nrmp);
             const double tot = fma(alpha.x, alpha.x, fma(alpha.y, alpha.y, sig));
             // inputs are pre-scaled to entries of order one, so a column whose squared norm is
             // below 2^-660 is rounding noise of an already reduced (rank-deficient) part:
@@ -476,22 +495,8 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             __syncthreads();
             // lane lam owns column lam (w) and row lam (y)
             double2 w = cz(), y = cz();
-            if (lam > j && lam < s) {
-#pragma unroll
-                for (int aa = 0; aa < P; ++aa) {
-                    const double2 pp = wpart[lam + S::WA * aa];
-                    w.x += pp.x;
-                    w.y += pp.y;
-                }
-            }
-            if (lam < s) {
-#pragma unroll
-                for (int bb = 0; bb < Q; ++bb) {
-                    const double2 pp = ypart[lam + S::YB * bb];
-                    y.x += pp.x;
-                    y.y += pp.y;
-                }
-            }
+            if (lam > j && lam < s) w = tree_sum<P, S::WA>(wpart + lam);
+            if (lam < s) y = tree_sum<Q, S::YB>(ypart + lam);
             const double2 wv = cmul(w, v);
             const double2 gam = make_double2(group_sum<L>(wv.x), group_sum<L>(wv.y));
             double2 y1 = y;
@@ -515,15 +520,20 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                         cfms_cj(h[t][u], yr[t], vcu);
                     }
                 }
-            // column j+1 -> colb for the next step (its owners have just updated it)
+            // column j+1 -> colb and its norm below row j+2 -> nrmp for the next step
+            // (its owners have just updated it)
             const int un = (j + 1) / Q, bn = (j + 1) % Q;
             if (b == bn && j + 3 < s) {
 #pragma unroll
                 for (int u = 0; u < C; ++u)
                     if (u == un) {
+                        double part = 0.0;
 #pragma unroll
-                        for (int t = 0; t < R; ++t)
+                        for (int t = 0; t < R; ++t) {
                             if (a + P * t < SM) colb[a + P * t] = h[t][u];
+                            if (a + P * t >= j + 3) part = fma(h[t][u].x, h[t][u].x, fma(h[t][u].y, h[t][u].y, part));
+                        }
+                        nrmp[a] = part;
                     }
             }
         }
