@@ -171,6 +171,7 @@ __device__ __forceinline__ double2 charpoly_lanes(const double2* __restrict__ gt
             for (int k = 0; k < 8; ++k)
                 if (c0 + k < K) cfma(acc[k & 1], gv[k], cr[c0 + k]);
         }
+        __builtin_amdgcn_s_setprio(2);        // the reduction and shift form the serial chain
         double2 tot = cadd(acc[0], acc[1]);
         if (SPLIT >= 4) { tot.x += swizzle_d<0x401F>(tot.x); tot.y += swizzle_d<0x401F>(tot.y); }   // lane ^ 16
         if (SPLIT >= 2) { tot.x = halves_sum(tot.x); tot.y = halves_sum(tot.y); }               // + lane ^ 32
@@ -186,6 +187,7 @@ __device__ __forceinline__ double2 charpoly_lanes(const double2* __restrict__ gt
         }
         if (bout && i < S && d == dtop && h == 0) bout[i] = ci;   // bout has S entries
         prev = ci;
+        __builtin_amdgcn_s_setprio(0);
         // keep each step's reads within the step: hoisting them across steps only
         // raises register pressure (and occupancy is what hides their latency)
         __builtin_amdgcn_sched_barrier(0);
@@ -443,6 +445,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             nrmp[a] = part;
         }
         for (int j = 0; j + 2 < s; ++j) {
+            __builtin_amdgcn_s_setprio(2);    // the reflector's serial part issues first
             __syncthreads();                  // column j is in colb, its row-group norms in nrmp
             const double2 x = (lam > j && lam < s) ? colb[lam] : cz();
             const double2 alpha = colb[j + 1];
@@ -474,6 +477,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             for (int t = 0; t < R; ++t) vr[t] = (a + P * t < SM) ? vv[a + P * t] : cz();
             const int ulo = (j + 1) / Q;      // column slots left of ulo hold only columns <= j
 
+            __builtin_amdgcn_s_setprio(0);
             // one pass: w partials (over own rows) and y partials (over own columns)
             double2 yp[R];
 #pragma unroll
@@ -492,6 +496,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                 }
 #pragma unroll
             for (int t = 0; t < R; ++t) ypart[a + P * t + S::YB * b] = yp[t];
+            __builtin_amdgcn_s_setprio(2);
             __syncthreads();
             // lane lam owns column lam (w) and row lam (y)
             double2 w = cz(), y = cz();
@@ -509,6 +514,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             double2 yr[R];
 #pragma unroll
             for (int t = 0; t < R; ++t) yr[t] = (a + P * t < SM) ? yb[a + P * t] : cz();
+            __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int u = 0; u < C; ++u)
                 if (u >= ulo) {
