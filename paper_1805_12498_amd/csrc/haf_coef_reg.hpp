@@ -526,6 +526,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                         cfms_cj(h[t][u], yr[t], vcu);
                     }
                 }
+            __builtin_amdgcn_s_setprio(2);
             // column j+1 -> colb and its norm below row j+2 -> nrmp for the next step
             // (its owners have just updated it)
             const int un = (j + 1) / Q, bn = (j + 1) % Q;
@@ -545,6 +546,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
         }
 
         }
+        __builtin_amdgcn_s_setprio(2);        // table, scaling walk: LDS latency chains
         // ---- the last subdiagonal entry (no reflector acts on it)
 #pragma unroll
         for (int t = 0; t < R; ++t)
@@ -579,6 +581,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
         }
         __syncthreads();
 
+        __builtin_amdgcn_s_setprio(0);
         // ---- characteristic polynomials
         if (CP == 0) {                        // each group: lane lam = degree d
             double2 cs = cz();
