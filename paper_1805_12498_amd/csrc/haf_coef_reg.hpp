@@ -22,6 +22,12 @@
 //    Q) partials, and the result is read back by the lanes that need it.  On
 //    gfx950 a 16-byte LDS read costs about one FP64 FMA, far less than moving the
 //    same bytes with DPP, swizzle or readlane;
+//  * the column norm each reflector needs comes from the column's owners: when
+//    they broadcast the column they also store the sum of |h|^2 over their rows,
+//    and every lane adds the P row-group values in the same fixed order;
+//  * the wave raises its issue priority over the serial parts of a step (the
+//    reflector, the partial sums, the broadcasts) and lowers it over the FMA
+//    passes, so that the other wave on the SIMD keeps the FMA pipe busy;
 //  * the characteristic polynomial is built with lanes over the degree d and the
 //    polynomials c_r in registers, fully unrolled for the exact s (so register
 //    slots and LDS offsets are static); the scaled Hessenberg entries g_{r,i} come
@@ -461,7 +467,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             if (!skip) {
                 // reflector P = I - tau v v^H with v unnormalised: v_{j+1} = d = alpha - beta,
                 // v_r = x_r below it, tau = -1 / (beta conj(d)) = -d / (beta |d|^2); the same P
-                // as v_{j+1} = 1, tau = (beta - alpha) / beta, for one division instead of three
+                // as v_{j+1} = 1, tau = (beta - alpha) / beta, for one reciprocal instead of three divisions
                 const double nrm = sqrt_pos(tot);
                 bet = alpha.x >= 0.0 ? -nrm : nrm;
                 const double2 d = make_double2(alpha.x - bet, alpha.y);
