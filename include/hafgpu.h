@@ -166,9 +166,11 @@ int haf_batched_plan(const int32_t* h_n, const uint8_t* h_kind, int count, int32
 /* Free every cached workspace of every device (waits for the device first). */
 int haf_release_workspaces(void);
 
-/* Kernel path selection (for testing and tuning): 0 = automatic, 1 = LDS
- * kernel only (Householder), 2 = register-tiled kernels with Householder
- * reflections, 3 = as 2 with one full wave per matrix above s = 16,
+/* Kernel path selection (for testing and tuning): 0 = automatic (for n <= 32
+ * all size classes of a matrix go out in one coefficient launch per layout and
+ * one series launch), 1 = LDS kernel only (Householder), 2 = register-tiled
+ * kernels with Householder reflections, one launch pair per size class (bitwise
+ * the results of 0), 3 = as 2 with one full wave per matrix above s = 16,
  * 4 = register-tiled kernels with the Hessenberg form by elimination with row
  * and column exchanges.  All reach the same characteristic polynomial (any
  * similarity does, App. B); they differ in rounding.  Process-wide. */

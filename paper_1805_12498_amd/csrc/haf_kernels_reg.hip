@@ -31,6 +31,68 @@ HAF_REG_NARROW(HAF_INST_REG_EL)
 
 int reg_max_s() { return 48; }
 
+// Several chunks of one matrix: the workgroup finds its chunk in the table (a
+// short uniform scan), then runs the same per-subset body as k_coef_reg.
+template <int P, int Q, int R, int C, int CP, bool LOOPS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 ? 2 : 1))) void k_coef_reg_multi(
+    const double2* __restrict__ A, int lda, int N, const int* __restrict__ d_exp, double2* __restrict__ coef,
+    MultiChunks mc) {
+    using S = RegShape<P, Q, R, C>;
+    __shared__ double2 lds[S::W * S::PER];
+    const int e = d_exp ? *d_exp : 0;
+    int c = 0;
+    while (c + 1 < mc.nc && (int)blockIdx.x >= mc.gstart[c + 1]) ++c;
+    const int groups = (mc.gstart[c + 1] - mc.gstart[c]) * S::W;
+    const int count = mc.count[c];
+    const int span = (count + groups - 1) / groups;
+    coef_reg_span<P, Q, R, C, CP, LOOPS, false>(lds, A, lda, N, mc.m[c], mc.rank0[c], count, nullptr,
+                                                ldexp(1.0, -2 * e), ldexp(1.0, -e), coef + mc.coff[c], count,
+                                                ((int)blockIdx.x - mc.gstart[c]) * S::W, span, threadIdx.x);
+}
+
+#define HAF_INST_REG_MULTI(P, Q, R, C, CP, LO, HI)                                                           \
+    template __global__ void k_coef_reg_multi<P, Q, R, C, CP, false>(const double2*, int, int, const int*,   \
+                                                                     double2*, MultiChunks);                 \
+    template __global__ void k_coef_reg_multi<P, Q, R, C, CP, true>(const double2*, int, int, const int*,    \
+                                                                    double2*, MultiChunks);
+HAF_REG_NARROW(HAF_INST_REG_MULTI)
+
+int reg_layout_index(int s) {
+    int i = 0;
+#define HAF_IDX(P, Q, R, C, CP, LO, HI) \
+    if (s > LO && s <= HI) return i;    \
+    ++i;
+    HAF_REG_NARROW(HAF_IDX)
+#undef HAF_IDX
+    return -1;
+}
+
+hipError_t launch_coef_reg_multi(int s_max, bool loops, int grid_waves, hipStream_t st, const double2* A, int lda,
+                                 int N, const int* d_exp, double2* coef, MultiChunks mc) {
+    if (mc.nc < 1 || mc.nc > kMultiMax) return hipErrorInvalidValue;
+#define HAF_TRY_MULTI(P, Q, R, C, CP, LO, HI)                                                                 \
+    if (s_max > LO && s_max <= HI) {                                                                          \
+        constexpr int W = RegShape<P, Q, R, C>::W;                                                            \
+        int g = 0;                                                                                            \
+        for (int c = 0; c < mc.nc; ++c) {                                                                     \
+            const int s = 2 * mc.m[c];                                                                        \
+            if (s <= LO || s > HI || mc.count[c] <= 0) return hipErrorInvalidValue;                           \
+            mc.gstart[c] = g;                                                                                 \
+            const int b = (mc.count[c] + W - 1) / W;                                                          \
+            g += b < grid_waves ? b : grid_waves;                                                             \
+        }                                                                                                     \
+        mc.gstart[mc.nc] = g;                                                                                 \
+        if (loops) hipLaunchKernelGGL((k_coef_reg_multi<P, Q, R, C, CP, true>), dim3(g), dim3(64), 0, st, A,   \
+                                      lda, N, d_exp, coef, mc);                                               \
+        else hipLaunchKernelGGL((k_coef_reg_multi<P, Q, R, C, CP, false>), dim3(g), dim3(64), 0, st, A, lda,  \
+                                N, d_exp, coef, mc);                                                          \
+        return hipGetLastError();                                                                             \
+    }
+    HAF_REG_NARROW(HAF_TRY_MULTI)
+#undef HAF_TRY_MULTI
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_coef_reg(int s, bool loops, int grid_waves, hipStream_t st, const double2* A, int lda, int N,
                            int m, uint64_t rank0, int count, const uint32_t* masks, const int* d_exp,
                            double2* coef, int64_t cstride, bool wide, bool elim) {

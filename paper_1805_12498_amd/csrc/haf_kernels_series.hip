@@ -19,6 +19,29 @@ namespace hafgpu {
 
 constexpr int kSeriesBlock = 256;
 
+// Signed double-double sum of one term per thread by a fixed tree; thread 0
+// stores (re_hi, re_lo, im_hi, im_lo) at out.
+__device__ __forceinline__ void block_partial(double sign, double2 f, double* __restrict__ out) {
+    __shared__ double sh[4][kSeriesBlock];
+    const int tid = threadIdx.x;
+    sh[0][tid] = sign * f.x;
+    sh[1][tid] = 0.0;
+    sh[2][tid] = sign * f.y;
+    sh[3][tid] = 0.0;
+    __syncthreads();
+    for (int st = kSeriesBlock / 2; st > 0; st >>= 1) {
+        if (tid < st) {
+            dd r = dd_add(dd{ sh[0][tid], sh[1][tid] }, dd{ sh[0][tid + st], sh[1][tid + st] });
+            dd i = dd_add(dd{ sh[2][tid], sh[3][tid] }, dd{ sh[2][tid + st], sh[3][tid + st] });
+            sh[0][tid] = r.hi; sh[1][tid] = r.lo; sh[2][tid] = i.hi; sh[3][tid] = i.lo;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out[0] = sh[0][0]; out[1] = sh[1][0]; out[2] = sh[2][0]; out[3] = sh[3][0];
+    }
+}
+
 // One block = kSeriesBlock subsets.  If terms != nullptr the unsigned f(Z) are
 // written out (no sum); otherwise the block's signed double-double partial goes
 // to partials[4 * (slot0 + blockIdx.x) + {re_hi, re_lo, im_hi, im_lo}].
@@ -36,25 +59,22 @@ __global__ __launch_bounds__(kSeriesBlock) void k_series(const double2* __restri
         if (t < count) terms[t] = make_double2(ldexp(f.x, e2n), ldexp(f.y, e2n));
         return;
     }
-    __shared__ double sh[4][kSeriesBlock];
-    const int tid = threadIdx.x;
-    sh[0][tid] = sign * f.x;
-    sh[1][tid] = 0.0;
-    sh[2][tid] = sign * f.y;
-    sh[3][tid] = 0.0;
-    __syncthreads();
-    for (int st = kSeriesBlock / 2; st > 0; st >>= 1) {
-        if (tid < st) {
-            dd r = dd_add(dd{ sh[0][tid], sh[1][tid] }, dd{ sh[0][tid + st], sh[1][tid + st] });
-            dd i = dd_add(dd{ sh[2][tid], sh[3][tid] }, dd{ sh[2][tid + st], sh[3][tid + st] });
-            sh[0][tid] = r.hi; sh[1][tid] = r.lo; sh[2][tid] = i.hi; sh[3][tid] = i.lo;
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        double* o = partials + 4 * (slot0 + blockIdx.x);
-        o[0] = sh[0][0]; o[1] = sh[1][0]; o[2] = sh[2][0]; o[3] = sh[3][0];
-    }
+    block_partial(sign, f, partials + 4 * (slot0 + blockIdx.x));
+}
+
+// Several chunks of one matrix (N <= 16): block b of chunk c covers the chunk's
+// subsets b*kSeriesBlock.. and writes slot slot0[c] + b, as k_series would.
+template <int N, bool LOOPS>
+__global__ __launch_bounds__(kSeriesBlock) void k_series_multi(const double2* __restrict__ coef,
+                                                               double* __restrict__ partials, MultiChunks mc) {
+    int c = 0;
+    while (c + 1 < mc.nc && (int)blockIdx.x >= mc.gstart[c + 1]) ++c;
+    const int lb = (int)blockIdx.x - mc.gstart[c];
+    const int t = lb * kSeriesBlock + threadIdx.x;
+    const int count = mc.count[c];
+    double2 f = cz();
+    if (t < count) f = subset_series_upto<N, LOOPS>(coef + mc.coff[c], count, t, N);
+    block_partial(mc.sign[c], f, partials + 4 * (mc.slot0[c] + lb));
 }
 
 #define HAF_INST_SERIES(NN)                                                                                    \
@@ -70,6 +90,29 @@ HAF_INST_SERIES(17) HAF_INST_SERIES(18) HAF_INST_SERIES(19) HAF_INST_SERIES(20)
 HAF_INST_SERIES(21) HAF_INST_SERIES(22) HAF_INST_SERIES(23) HAF_INST_SERIES(24)
 HAF_INST_SERIES(25) HAF_INST_SERIES(26) HAF_INST_SERIES(27) HAF_INST_SERIES(28)
 HAF_INST_SERIES(29) HAF_INST_SERIES(30) HAF_INST_SERIES(31) HAF_INST_SERIES(32)
+
+using SeriesMultiFn = void (*)(const double2*, double*, MultiChunks);
+#define HAF_SM(NN) { k_series_multi<NN, false>, k_series_multi<NN, true> },
+static const SeriesMultiFn g_series_multi[17][2] = {
+    { nullptr, nullptr },
+    HAF_SM(1) HAF_SM(2) HAF_SM(3) HAF_SM(4) HAF_SM(5) HAF_SM(6) HAF_SM(7) HAF_SM(8)
+    HAF_SM(9) HAF_SM(10) HAF_SM(11) HAF_SM(12) HAF_SM(13) HAF_SM(14) HAF_SM(15) HAF_SM(16)
+};
+#undef HAF_SM
+
+hipError_t launch_series_multi(int N, bool loops, hipStream_t st, const double2* coef, double* partials,
+                               MultiChunks mc) {
+    if (N < 1 || N > 16 || mc.nc < 1 || mc.nc > kMultiMax) return hipErrorInvalidValue;
+    int g = 0;
+    for (int c = 0; c < mc.nc; ++c) {
+        if (mc.count[c] <= 0) return hipErrorInvalidValue;
+        mc.gstart[c] = g;
+        g += (mc.count[c] + kSeriesBlock - 1) / kSeriesBlock;
+    }
+    mc.gstart[mc.nc] = g;
+    hipLaunchKernelGGL(g_series_multi[N][loops ? 1 : 0], dim3(g), dim3(kSeriesBlock), 0, st, coef, partials, mc);
+    return hipGetLastError();
+}
 
 // Fixed-order double-double sum of nslots partials (one block of 256 threads):
 // thread t folds slots t, t+256, ... in order, then a fixed tree.  Writes the

@@ -23,6 +23,34 @@ hipError_t launch_coef_reg(int s, bool loops, int grid_waves, hipStream_t st, co
                            double2* coef, int64_t cstride, bool wide, bool elim);
 int reg_max_s();
 
+// Several chunks of one matrix in one launch (each chunk: one size class m,
+// ranks rank0 .. rank0 + count - 1).  Chunk c owns the workgroups
+// gstart[c] .. gstart[c+1] - 1; the launch wrappers fill gstart.  Each chunk's
+// coefficients sit at coef + coff[c] with stride count[c], exactly as a
+// one-chunk launch would write them, and each series block of a chunk leaves its
+// partial in the slot a one-chunk launch would use, so the results are bitwise
+// those of one launch per chunk.
+constexpr int kMultiMax = 16;
+struct MultiChunks {
+    int nc;                              // chunks in the launch (1..kMultiMax)
+    int gstart[kMultiMax + 1];
+    int m[kMultiMax];
+    int count[kMultiMax];
+    int64_t coff[kMultiMax];             // offset of the chunk's coefficients (complex values)
+    uint64_t rank0[kMultiMax];
+    int64_t slot0[kMultiMax];            // first partial slot (series)
+    double sign[kMultiMax];              // (-1)^(N - m) (series)
+};
+// Register-tiled coefficients of several chunks whose sizes s = 2m all fall in
+// the range of one default layout (s_max names it).
+hipError_t launch_coef_reg_multi(int s_max, bool loops, int grid_waves, hipStream_t st, const double2* A, int lda,
+                                 int N, const int* d_exp, double2* coef, MultiChunks mc);
+// Index of the default layout that serves subsets of s rows (-1 above the table).
+int reg_layout_index(int s);
+// Series + signed block partials of several chunks (N <= 16).
+hipError_t launch_series_multi(int N, bool loops, hipStream_t st, const double2* coef, double* partials,
+                               MultiChunks mc);
+
 // Exponent e of the exact input scaling (off-diagonal by 2^-2e, diagonal by
 // 2^-e; the result is multiplied back by 2^(2eN)), written to *d_exp.
 hipError_t launch_prescale(hipStream_t st, const double2* A, int n, int lda, int* d_exp);

@@ -264,6 +264,63 @@ int launch_coef_chunk(int dev, const double2* dA, int lda, int N, int m, uint64_
     return hip_check(e, "coefficient kernel launch");
 }
 
+// The same work as the per-chunk loop below, in fewer launches: chunk c's
+// coefficients at coef + coff[c] (stride count[c]), partial slots as planned.
+static int enqueue_haf_multi(int dev, Workspace* w, const Plan& plan, const double2* dA, int lda, bool loops,
+                             double* out_dd, double2* out, hipStream_t st) {
+    std::vector<int64_t> coff(plan.chunks.size());
+    int64_t total = 0;
+    for (size_t c = 0; c < plan.chunks.size(); ++c) {
+        coff[c] = total;
+        total += (int64_t)plan.chunks[c].count * plan.ncoef;
+    }
+    int rc = workspace_reserve(w, st, (size_t)total * sizeof(double2), (size_t)plan.nslots * 4 * sizeof(double), 64);
+    if (rc) return rc;
+    int* d_exp = (int*)w->aux;
+    if ((rc = hip_check(launch_prescale(st, dA, plan.n, lda, d_exp), "prescale kernel launch"))) return rc;
+    // coefficients: one launch per run of consecutive chunks that share a layout
+    for (size_t c0 = 0; c0 < plan.chunks.size();) {
+        const int lay = reg_layout_index(2 * plan.chunks[c0].m);
+        MultiChunks mc{};
+        double flops = 0.0;
+        int64_t subsets = 0;
+        size_t c1 = c0;
+        for (; c1 < plan.chunks.size() && reg_layout_index(2 * plan.chunks[c1].m) == lay; ++c1) {
+            const Chunk& ch = plan.chunks[c1];
+            const int k = mc.nc++;
+            mc.m[k] = ch.m;
+            mc.count[k] = ch.count;
+            mc.coff[k] = coff[c1];
+            mc.rank0[k] = ch.rank0;
+            flops += (double)ch.count * coef_model_flops(2 * ch.m, plan.N, loops);
+            subsets += ch.count;
+        }
+        const int pidx = prof_begin(st, 0, flops, subsets);
+        const hipError_t e = launch_coef_reg_multi(2 * plan.chunks[c1 - 1].m, loops, device_cus(dev) * 16, st, dA,
+                                                   lda, plan.N, d_exp, w->coef, mc);
+        prof_end(pidx, st);
+        if ((rc = hip_check(e, "coefficient kernel launch"))) return rc;
+        c0 = c1;
+    }
+    MultiChunks ms{};
+    int64_t subsets = 0;
+    for (size_t c = 0; c < plan.chunks.size(); ++c) {
+        const Chunk& ch = plan.chunks[c];
+        ms.m[c] = ch.m;
+        ms.count[c] = ch.count;
+        ms.coff[c] = coff[c];
+        ms.slot0[c] = ch.slot0;
+        ms.sign[c] = ((plan.N - ch.m) & 1) ? -1.0 : 1.0;
+        subsets += ch.count;
+    }
+    ms.nc = (int)plan.chunks.size();
+    const int pidx = prof_begin(st, 1, 0.0, subsets);
+    const hipError_t e = launch_series_multi(plan.N, loops, st, w->coef, w->part, ms);
+    prof_end(pidx, st);
+    if ((rc = hip_check(e, "series kernel launch"))) return rc;
+    return hip_check(launch_reduce(st, w->part, plan.nslots, out_dd, out, d_exp, plan.N), "reduce kernel launch");
+}
+
 // Enqueue one hafnian of an n x n device matrix (n even, 2 <= n <= 64).
 int enqueue_haf(const double2* dA, int n, int lda, int kind, double* out_dd, double2* out, hipStream_t st) {
     int dev = 0;
@@ -272,10 +329,15 @@ int enqueue_haf(const double2* dA, int n, int lda, int kind, double* out_dd, dou
     Workspace* w = nullptr;
     if ((rc = workspace_for(st, &w))) return rc;
     const Plan plan = make_plan(n, kind, kChunk);
+    const bool loops = kind == HAF_KIND_LHAF;
+    // Small matrices (N <= 16, one chunk per size class) on the default path: all
+    // coefficients stay resident, one launch per layout and one series launch
+    // replace a launch pair per size class (launch overhead dominates there)
+    if (g_kernel_path == 0 && plan.N <= 16 && (int)plan.chunks.size() <= kMultiMax)
+        return enqueue_haf_multi(dev, w, plan, dA, lda, loops, out_dd, out, st);
     const size_t coef_bytes = (size_t)plan.max_chunk * plan.ncoef * sizeof(double2);
     const size_t part_bytes = (size_t)plan.nslots * 4 * sizeof(double);
     if ((rc = workspace_reserve(w, st, coef_bytes, part_bytes, 64))) return rc;
-    const bool loops = kind == HAF_KIND_LHAF;
     int* d_exp = (int*)w->aux;
     if ((rc = hip_check(launch_prescale(st, dA, n, lda, d_exp), "prescale kernel launch"))) return rc;
     for (const Chunk& c : plan.chunks) {

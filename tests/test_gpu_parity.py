@@ -203,6 +203,23 @@ def test_bitwise_deterministic(hg):
     assert a == b
 
 
+@pytest.mark.parametrize("n", [2, 4, 8, 13, 16, 21, 24, 28, 32])
+def test_multi_chunk_launches_bitwise(hg, n):
+    """Up to n = 32 the default path runs all size classes of a matrix in a few
+    multi-chunk launches; path 2 (same kernels, one launch pair per size class)
+    must give bitwise the same double-double result."""
+    for kind in (0, 1):
+        A = gi.gaussian_symmetric(n, 7000 + n)
+        try:
+            hg.set_kernel_path(0)
+            r0 = hg.haf_host(A, kind, x2=True)
+            hg.set_kernel_path(2)
+            r2 = hg.haf_host(A, kind, x2=True)
+        finally:
+            hg.set_kernel_path(int(os.environ.get("HAFGPU_KERNEL_PATH", "0")))
+        assert tuple(r0) == tuple(r2), (n, kind, r0, r2)
+
+
 def test_errors(hg):
     from paper_1805_12498_amd._native import HafError
     A = rand_sym(6, 1)
