@@ -140,13 +140,16 @@ typedef struct {
                            chunk at 16 rows, scaled by (16/s)^3 for s rows              */
     int waves_per_cu;   /* persistent kernel: workgroups per CU, 0 = as many as fit    */
     int streams;        /* streams the batch is spread over, 1..16 (default 8)         */
+    int grouped;        /* 1 (default): matrices with n <= 32 share launches with the other
+                           matrices of their size and kind, on the first pool stream;
+                           0: every matrix runs its own single-matrix launches           */
 } haf_batched_config;
 
 int haf_batched_get_config(haf_batched_config* cfg);
 /* HAF_E_INVALID_ARG for values out of range.  No setting changes a result. */
 int haf_batched_set_config(const haf_batched_config* cfg);
 /* Autotuner: runs the given batch (same arguments as haf_batched_c128; d_out
- * receives the results) with 1, 2, 4, 8 and 16 streams, times each run with
+ * receives the results) with 1, 2, 4, 8 and 16 streams, grouped and not, times each run with
  * HIP events on `stream`, makes the fastest the current configuration and
  * returns it in *best and its time in *best_ms.  Synchronous. */
 int haf_batched_tune(const haf_cplx* dA_packed, const int64_t* h_offsets, const int32_t* h_n,

@@ -61,7 +61,7 @@ class Profile(ctypes.Structure):
 
 class BatchedConfig(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int), ("group_work", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
-                ("streams", ctypes.c_int)]
+                ("streams", ctypes.c_int), ("grouped", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -195,8 +195,9 @@ def batched_config() -> dict:
     return {f: getattr(c, f) for f, _ in BatchedConfig._fields_}
 
 
-def set_batched_config(layout: int = 0, group_work: int = 16, waves_per_cu: int = 0, streams: int = 8):
-    c = BatchedConfig(layout, group_work, waves_per_cu, streams)
+def set_batched_config(layout: int = 0, group_work: int = 16, waves_per_cu: int = 0, streams: int = 8,
+                       grouped: int = 1):
+    c = BatchedConfig(layout, group_work, waves_per_cu, streams, grouped)
     check(load().haf_batched_set_config(ctypes.byref(c)))
 
 

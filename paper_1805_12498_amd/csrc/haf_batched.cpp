@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -18,7 +19,7 @@ namespace hafgpu {
 
 // ------------------------------------------------------------------ planner
 static std::mutex g_bcfg_mu;
-static haf_batched_config g_bcfg = { 0, 16, 0, 8 };
+static haf_batched_config g_bcfg = { 0, 16, 0, 8, 1 };
 
 haf_batched_config batch_config() {
     std::lock_guard<std::mutex> lk(g_bcfg_mu);
@@ -384,6 +385,161 @@ static double item_cost(int n, int kind) {
     return f;
 }
 
+// ------------------------------------------------------------------ same-size groups
+// Matrices with 2 <= n <= 32 (after the odd-n loop-hafnian padding) go through
+// shared launches per (n, kind): one prologue, one coefficient launch per layout
+// run and sub-batch, one series launch per sub-batch, one reduction per group.
+// Each matrix keeps the single-matrix path's coefficients, slots and reduction.
+constexpr size_t kGroupCoefBudget = size_t(256) << 20;   // coefficient bytes per sub-batch
+
+static bool groupable(int n, int kind) {
+    if (n == 0 || (n % 2 == 1 && kind == HAF_KIND_HAF)) return false;   // constant results
+    const int eff = n % 2 == 1 ? n + 1 : n;
+    return eff >= 2 && eff <= 32;
+}
+
+static int run_grouped(const double2* dA, const int64_t* offs, const int32_t* ns, const uint8_t* kinds,
+                       const std::vector<int>& list, double2* d_out, hipStream_t st) {
+    if (list.empty()) return HAF_OK;
+    BatchWS* w = nullptr;
+    int rc = batch_ws(st, &w);
+    if (rc) return rc;
+    // matrices ordered by (n, kind), stable in the caller's order
+    std::vector<int> order(list);
+    auto eff = [&](int t) { return ns[t] % 2 == 1 ? ns[t] + 1 : ns[t]; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return eff(a) != eff(b) ? eff(a) < eff(b) : kinds[a] < kinds[b];
+    });
+    const int ni = (int)order.size();
+    std::vector<GroupItem> items((size_t)ni);
+    std::vector<int64_t> padoff((size_t)ni, -1);             // offset of a padded copy in w->pad
+    struct Launch { int kind; int s_max; int N; bool loops; int blocks; size_t first; int nch; };
+    std::vector<GroupChunk> chunks;
+    std::vector<Launch> launches;                            // kind 0 coef, 1 series, 2 reduce (first = item)
+    int64_t slot = 0, pad_elems = 0, coef_max = 0;
+    for (int g0 = 0; g0 < ni;) {
+        const int n = eff(order[g0]), kind = kinds[order[g0]];
+        int g1 = g0;
+        while (g1 < ni && eff(order[g1]) == n && kinds[order[g1]] == kind) ++g1;
+        const Plan plan = make_plan(n, kind, kChunk);
+        const bool loops = kind == HAF_KIND_LHAF;
+        for (int j = g0; j < g1; ++j) {
+            const int t = order[j];
+            GroupItem& it = items[(size_t)j];
+            it.src = dA + offs[t];
+            it.src_n = ns[t];
+            it.src_lda = std::max(ns[t], 1);
+            it.n = n;
+            it.A = it.src;
+            it.lda = it.src_lda;
+            if (n != ns[t]) {                            // odd-n loop hafnian: dense padded copy
+                padoff[(size_t)j] = pad_elems;
+                it.lda = n;
+                pad_elems += (int64_t)n * n;
+            }
+            it.out = d_out + t;
+            it.slot_base = slot;
+            it.nslots = plan.nslots;
+            slot += plan.nslots;
+        }
+        // sub-batches bounded by the coefficient budget
+        const int64_t per_item = (int64_t)((1u << plan.N) - 1) * plan.ncoef;
+        const int per_batch = (int)std::max<int64_t>(1, (int64_t)(kGroupCoefBudget / sizeof(double2)) / per_item);
+        for (int b0 = g0; b0 < g1; b0 += per_batch) {
+            const int b1 = std::min(g1, b0 + per_batch);
+            coef_max = std::max<int64_t>(coef_max, (int64_t)(b1 - b0) * per_item);
+            // coefficient offsets: item-major, classes in plan order
+            std::vector<int64_t> coff((size_t)(b1 - b0) * plan.chunks.size());
+            int64_t off = 0;
+            for (int j = b0; j < b1; ++j)
+                for (size_t c = 0; c < plan.chunks.size(); ++c) {
+                    coff[(size_t)(j - b0) * plan.chunks.size() + c] = off;
+                    off += (int64_t)plan.chunks[c].count * plan.ncoef;
+                }
+            // one coefficient launch per run of classes sharing a layout
+            for (size_t c0 = 0; c0 < plan.chunks.size();) {
+                const int lay = reg_layout_index(2 * plan.chunks[c0].m);
+                size_t c1 = c0;
+                while (c1 < plan.chunks.size() && reg_layout_index(2 * plan.chunks[c1].m) == lay) ++c1;
+                const int s_max = 2 * plan.chunks[c1 - 1].m;
+                Launch L{ 0, s_max, plan.N, loops, 0, chunks.size(), 0 };
+                for (int j = b0; j < b1; ++j)
+                    for (size_t c = c0; c < c1; ++c) {
+                        GroupChunk ch{};
+                        ch.item = j;
+                        ch.m = plan.chunks[c].m;
+                        ch.count = plan.chunks[c].count;
+                        ch.gstart = L.blocks;
+                        ch.coff = coff[(size_t)(j - b0) * plan.chunks.size() + c];
+                        L.blocks += group_coef_blocks(s_max, ch.count);
+                        chunks.push_back(ch);
+                        ++L.nch;
+                    }
+                launches.push_back(L);
+                c0 = c1;
+            }
+            Launch S{ 1, 0, plan.N, loops, 0, chunks.size(), 0 };
+            for (int j = b0; j < b1; ++j)
+                for (size_t c = 0; c < plan.chunks.size(); ++c) {
+                    GroupChunk ch{};
+                    ch.item = j;
+                    ch.m = plan.chunks[c].m;
+                    ch.count = plan.chunks[c].count;
+                    ch.gstart = S.blocks;
+                    ch.coff = coff[(size_t)(j - b0) * plan.chunks.size() + c];
+                    ch.slot = items[(size_t)j].slot_base + plan.chunks[c].slot0;
+                    ch.sign = ((plan.N - ch.m) & 1) ? -1.0 : 1.0;
+                    S.blocks += group_series_blocks(ch.count);
+                    chunks.push_back(ch);
+                    ++S.nch;
+                }
+            launches.push_back(S);
+        }
+        launches.push_back(Launch{ 2, 0, plan.N, loops, 0, (size_t)g0, g1 - g0 });
+        g0 = g1;
+    }
+
+    // device buffers
+    if (pad_elems && (rc = grow((void**)&w->pad, &w->pad_cap, sizeof(double2) * (size_t)pad_elems, st))) return rc;
+    for (int j = 0; j < ni; ++j)
+        if (padoff[(size_t)j] >= 0) items[(size_t)j].A = w->pad + padoff[(size_t)j];
+    if ((rc = grow((void**)&w->coef, &w->coef_cap, sizeof(double2) * (size_t)std::max<int64_t>(coef_max, 1), st)))
+        return rc;
+    if ((rc = grow((void**)&w->part, &w->part_cap, sizeof(double) * 4 * (size_t)std::max<int64_t>(slot, 1), st)))
+        return rc;
+    if ((rc = grow((void**)&w->dstate, &w->dstate_cap, sizeof(int) * (size_t)ni, st))) return rc;
+    const size_t items_b = align256(sizeof(GroupItem) * items.size());
+    const size_t meta_b = items_b + align256(sizeof(GroupChunk) * std::max<size_t>(chunks.size(), 1));
+    if ((rc = grow((void**)&w->dmeta, &w->dmeta_cap, meta_b, st))) return rc;
+    if (w->staged_used && (rc = hip_check(hipEventSynchronize(w->staged), "event synchronize"))) return rc;
+    if ((rc = grow_pinned(w, meta_b))) return rc;
+    std::memcpy(w->hmeta, items.data(), sizeof(GroupItem) * items.size());
+    if (!chunks.empty()) std::memcpy(w->hmeta + items_b, chunks.data(), sizeof(GroupChunk) * chunks.size());
+    if ((rc = hip_check(hipMemcpyAsync(w->dmeta, w->hmeta, meta_b, hipMemcpyHostToDevice, st), "group table upload")))
+        return rc;
+    if ((rc = hip_check(hipEventRecord(w->staged, st), "event record"))) return rc;
+    w->staged_used = true;
+    const GroupItem* ditems = (const GroupItem*)w->dmeta;
+    const GroupChunk* dch = (const GroupChunk*)(w->dmeta + items_b);
+    int* exps = w->dstate;
+
+    if ((rc = hip_check(launch_group_prologue(st, ditems, ni, exps), "group prologue launch"))) return rc;
+    for (const Launch& L : launches) {
+        hipError_t e = hipSuccess;
+        if (L.kind == 0) {
+            const int pidx = prof_begin(st, 2, 0.0, 0);
+            e = launch_coef_reg_group(L.s_max, L.loops, L.blocks, st, ditems, dch + L.first, L.nch, L.N, exps, w->coef);
+            prof_end(pidx, st);
+        } else if (L.kind == 1) {
+            e = launch_series_group(L.N, L.loops, L.blocks, st, dch + L.first, L.nch, w->coef, w->part);
+        } else {
+            e = launch_reduce_group(st, ditems + L.first, L.nch, w->part, exps + L.first, L.N);
+        }
+        if ((rc = hip_check(e, "group kernel launch"))) return rc;
+    }
+    return HAF_OK;
+}
+
 int run_batched_streams(const double2* dA, const int64_t* offs, const int32_t* ns, const uint8_t* kinds, int count,
                         double2* d_out, hipStream_t st, const haf_batched_config& cfg) {
     int rc = check_batch_args(dA, offs, ns, kinds, count, d_out);
@@ -402,6 +558,21 @@ int run_batched_streams(const double2* dA, const int64_t* offs, const int32_t* n
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     std::vector<std::vector<int>> lists((size_t)nst);
     std::vector<double> load((size_t)nst, 0.0);
+    // same-size groups go out in shared launches on pool stream 0
+    std::vector<int> grouped;
+    if (cfg.grouped) {
+        std::vector<int> rest;
+        for (int t : order) {
+            if (groupable(ns[t], kinds[t])) {
+                grouped.push_back(t);
+                load[0] += cost[t];
+            } else {
+                rest.push_back(t);
+            }
+        }
+        std::sort(grouped.begin(), grouped.end());
+        order.swap(rest);
+    }
     for (int t : order) {
         const int p = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         lists[p].push_back(t);
@@ -421,6 +592,14 @@ int run_batched_streams(const double2* dA, const int64_t* offs, const int32_t* n
             msgs[p] = "hipSetDevice failed";
             return;
         }
+        if (p == 0 && !grouped.empty()) {
+            const int r = run_grouped(dA, offs, ns, kinds, grouped, d_out, pool->st[0]);
+            if (r) {
+                rcs[p] = r;
+                msgs[p] = last_error();
+                return;
+            }
+        }
         for (int t : lists[p]) {
             const int r = run_dev(dA + offs[t], ns[t], std::max(ns[t], 1), kinds[t], nullptr, d_out + t,
                                   pool->st[p]);
@@ -436,7 +615,7 @@ int run_batched_streams(const double2* dA, const int64_t* offs, const int32_t* n
     } else {
         std::vector<std::thread> th;
         for (int p = 0; p < nst; ++p)
-            if (!lists[p].empty()) th.emplace_back(worker, p);
+            if (!lists[p].empty() || (p == 0 && !grouped.empty())) th.emplace_back(worker, p);
         for (auto& x : th) x.join();
     }
     // join back: st waits for every pool stream (also after an error, so that
@@ -486,6 +665,8 @@ int haf_batched_set_config(const haf_batched_config* cfg) {
         return set_error(HAF_E_INVALID_ARG, "waves_per_cu %d not in 0..64", cfg->waves_per_cu);
     if (cfg->streams < 1 || cfg->streams > 16)
         return set_error(HAF_E_INVALID_ARG, "streams %d not in 1..16", cfg->streams);
+    if (cfg->grouped != 0 && cfg->grouped != 1)
+        return set_error(HAF_E_INVALID_ARG, "grouped %d not 0 or 1", cfg->grouped);
     set_batch_config(*cfg);
     return HAF_OK;
 }
@@ -502,11 +683,13 @@ int haf_batched_tune(const haf_cplx* dA_packed, const int64_t* h_offsets, const 
         return set_error(HAF_E_DEVICE, "hipEventCreate failed");
     std::vector<haf_batched_config> cand;
     const haf_batched_config keep = batch_config();
-    for (int nst : { 1, 2, 4, 8, 16 }) {
-        haf_batched_config c = keep;
-        c.streams = nst;
-        cand.push_back(c);
-    }
+    for (int grp : { 1, 0 })
+        for (int nst : { 1, 2, 4, 8, 16 }) {
+            haf_batched_config c = keep;
+            c.grouped = grp;
+            c.streams = nst;
+            cand.push_back(c);
+        }
     haf_batched_config pick = keep;
     double pick_ms = 1e300;
     for (const haf_batched_config& c : cand) {

@@ -57,6 +57,63 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 
                                                                     double2*, MultiChunks);
 HAF_REG_NARROW(HAF_INST_REG_MULTI)
 
+// Same-size matrices of a batch: the workgroup finds its chunk by a binary
+// search over the launch's chunk table (uniform), then runs the per-subset body.
+template <int P, int Q, int R, int C, int CP, bool LOOPS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 ? 2 : 1))) void k_coef_reg_group(
+    const GroupItem* __restrict__ items, const GroupChunk* __restrict__ chunks, int nchunks, int N,
+    const int* __restrict__ exps, double2* __restrict__ coef) {
+    using S = RegShape<P, Q, R, C>;
+    __shared__ double2 lds[S::W * S::PER];
+    const int blk = (int)blockIdx.x;
+    int lo = 0, hi = nchunks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (chunks[mid].gstart <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    const GroupChunk ch = chunks[lo];
+    const int gend = lo + 1 < nchunks ? chunks[lo + 1].gstart : (int)gridDim.x;
+    const int groups = (gend - ch.gstart) * S::W;
+    const int span = (ch.count + groups - 1) / groups;
+    const GroupItem it = items[ch.item];
+    const int e = exps[ch.item];
+    coef_reg_span<P, Q, R, C, CP, LOOPS, false>(lds, it.A, it.lda, N, ch.m, 0, ch.count, nullptr, ldexp(1.0, -2 * e),
+                                                ldexp(1.0, -e), coef + ch.coff, ch.count, (blk - ch.gstart) * S::W,
+                                                span, threadIdx.x);
+}
+
+#define HAF_INST_REG_GROUP(P, Q, R, C, CP, LO, HI)                                                          \
+    template __global__ void k_coef_reg_group<P, Q, R, C, CP, false>(const GroupItem*, const GroupChunk*,   \
+                                                                     int, int, const int*, double2*);       \
+    template __global__ void k_coef_reg_group<P, Q, R, C, CP, true>(const GroupItem*, const GroupChunk*,    \
+                                                                    int, int, const int*, double2*);
+HAF_REG_NARROW(HAF_INST_REG_GROUP)
+
+int group_coef_blocks(int s_max, int count) {
+#define HAF_GB(P, Q, R, C, CP, LO, HI) \
+    if (s_max > LO && s_max <= HI) return (count + RegShape<P, Q, R, C>::W - 1) / RegShape<P, Q, R, C>::W;
+    HAF_REG_NARROW(HAF_GB)
+#undef HAF_GB
+    return 0;
+}
+
+hipError_t launch_coef_reg_group(int s_max, bool loops, int blocks, hipStream_t st, const GroupItem* items,
+                                 const GroupChunk* chunks, int nchunks, int N, const int* exps, double2* coef) {
+    if (nchunks < 1 || blocks < 1) return hipErrorInvalidValue;
+#define HAF_TRY_GROUP(P, Q, R, C, CP, LO, HI)                                                                 \
+    if (s_max > LO && s_max <= HI) {                                                                          \
+        if (loops) hipLaunchKernelGGL((k_coef_reg_group<P, Q, R, C, CP, true>), dim3(blocks), dim3(64), 0, st, \
+                                      items, chunks, nchunks, N, exps, coef);                                 \
+        else hipLaunchKernelGGL((k_coef_reg_group<P, Q, R, C, CP, false>), dim3(blocks), dim3(64), 0, st,     \
+                                items, chunks, nchunks, N, exps, coef);                                       \
+        return hipGetLastError();                                                                             \
+    }
+    HAF_REG_NARROW(HAF_TRY_GROUP)
+#undef HAF_TRY_GROUP
+    return hipErrorInvalidValue;
+}
+
 int reg_layout_index(int s) {
     int i = 0;
 #define HAF_IDX(P, Q, R, C, CP, LO, HI) \

@@ -62,6 +62,27 @@ __global__ __launch_bounds__(kSeriesBlock) void k_series(const double2* __restri
     block_partial(sign, f, partials + 4 * (slot0 + blockIdx.x));
 }
 
+// Same-size matrices of a batch (N <= 16): the workgroup finds its chunk by a
+// binary search over the launch's chunk table, then as k_series.
+template <int N, bool LOOPS>
+__global__ __launch_bounds__(kSeriesBlock) void k_series_group(const GroupChunk* __restrict__ chunks, int nchunks,
+                                                               const double2* __restrict__ coef,
+                                                               double* __restrict__ partials) {
+    const int blk = (int)blockIdx.x;
+    int lo = 0, hi = nchunks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (chunks[mid].gstart <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    const GroupChunk ch = chunks[lo];
+    const int lb = blk - ch.gstart;
+    const int t = lb * kSeriesBlock + threadIdx.x;
+    double2 f = cz();
+    if (t < ch.count) f = subset_series_upto<N, LOOPS>(coef + ch.coff, ch.count, t, N);
+    block_partial(ch.sign, f, partials + 4 * (ch.slot + lb));
+}
+
 // Several chunks of one matrix (N <= 16): block b of chunk c covers the chunk's
 // subsets b*kSeriesBlock.. and writes slot slot0[c] + b, as k_series would.
 template <int N, bool LOOPS>
@@ -100,6 +121,25 @@ static const SeriesMultiFn g_series_multi[17][2] = {
 };
 #undef HAF_SM
 
+using SeriesGroupFn = void (*)(const GroupChunk*, int, const double2*, double*);
+#define HAF_SG(NN) { k_series_group<NN, false>, k_series_group<NN, true> },
+static const SeriesGroupFn g_series_group[17][2] = {
+    { nullptr, nullptr },
+    HAF_SG(1) HAF_SG(2) HAF_SG(3) HAF_SG(4) HAF_SG(5) HAF_SG(6) HAF_SG(7) HAF_SG(8)
+    HAF_SG(9) HAF_SG(10) HAF_SG(11) HAF_SG(12) HAF_SG(13) HAF_SG(14) HAF_SG(15) HAF_SG(16)
+};
+#undef HAF_SG
+
+int group_series_blocks(int count) { return (count + kSeriesBlock - 1) / kSeriesBlock; }
+
+hipError_t launch_series_group(int N, bool loops, int blocks, hipStream_t st, const GroupChunk* chunks, int nchunks,
+                               const double2* coef, double* partials) {
+    if (N < 1 || N > 16 || nchunks < 1 || blocks < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(g_series_group[N][loops ? 1 : 0], dim3(blocks), dim3(kSeriesBlock), 0, st, chunks, nchunks,
+                       coef, partials);
+    return hipGetLastError();
+}
+
 hipError_t launch_series_multi(int N, bool loops, hipStream_t st, const double2* coef, double* partials,
                                MultiChunks mc) {
     if (N < 1 || N > 16 || mc.nc < 1 || mc.nc > kMultiMax) return hipErrorInvalidValue;
@@ -117,9 +157,9 @@ hipError_t launch_series_multi(int N, bool loops, hipStream_t st, const double2*
 // Fixed-order double-double sum of nslots partials (one block of 256 threads):
 // thread t folds slots t, t+256, ... in order, then a fixed tree.  Writes the
 // double-double result (if out_dd) and its rounding to complex double (if out).
-__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partials, int64_t nslots,
-                                                          double* __restrict__ out_dd, double2* __restrict__ out,
-                                                          const int* __restrict__ d_exp, int N) {
+__device__ __forceinline__ void reduce_partials_block(const double* __restrict__ partials, int64_t nslots,
+                                                      double* __restrict__ out_dd, double2* __restrict__ out, int e,
+                                                      int N) {
     __shared__ double sh[4][256];
     const int tid = threadIdx.x;
     dd r{ 0.0, 0.0 }, i{ 0.0, 0.0 };
@@ -140,7 +180,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
     }
     if (tid == 0) {
         // undo the exact input scaling: haf(A) = 2^(2eN) haf(A')
-        const int e2n = d_exp ? 2 * N * (*d_exp) : 0;
+        const int e2n = 2 * N * e;
         const double rh = ldexp(sh[0][0], e2n), rl = ldexp(sh[1][0], e2n);
         const double ih = ldexp(sh[2][0], e2n), il = ldexp(sh[3][0], e2n);
         if (out_dd) { out_dd[0] = rh; out_dd[1] = rl; out_dd[2] = ih; out_dd[3] = il; }
@@ -148,12 +188,26 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
     }
 }
 
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partials, int64_t nslots,
+                                                          double* __restrict__ out_dd, double2* __restrict__ out,
+                                                          const int* __restrict__ d_exp, int N) {
+    reduce_partials_block(partials, nslots, out_dd, out, d_exp ? *d_exp : 0, N);
+}
+
+// One workgroup per matrix of a same-size group (the single-matrix reduction).
+__global__ __launch_bounds__(256) void k_reduce_group(const GroupItem* __restrict__ items,
+                                                       const double* __restrict__ partials,
+                                                       const int* __restrict__ exps, int N) {
+    const GroupItem it = items[blockIdx.x];
+    reduce_partials_block(partials + 4 * it.slot_base, it.nslots, nullptr, it.out, exps[blockIdx.x], N);
+}
+
 // Exponent of the exact input scaling.  With f the largest |Re|, |Im| of an
 // off-diagonal entry, e = floor(ilogb(f) / 2): the off-diagonal part scaled by
 // 2^-2e and the diagonal by 2^-e keep haf and lhaf exact up to the factor
 // 2^(2eN) (the scaling laws of Sec. 2: haf(mu A) = mu^(n/2) haf(A) and
 // lhaf(sqrt(mu) A_diag + mu A_off) = mu^(n/2) lhaf(A)).
-__global__ __launch_bounds__(256) void k_prescale(const double2* __restrict__ A, int n, int lda, int* __restrict__ d_exp) {
+__device__ __forceinline__ int prescale_exp_block(const double2* __restrict__ A, int n, int lda) {
     __shared__ double sh[256];
     double f = 0.0;
     for (int e = threadIdx.x; e < n * n; e += 256) {
@@ -169,12 +223,35 @@ __global__ __launch_bounds__(256) void k_prescale(const double2* __restrict__ A,
         if (threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double m = sh[0];
-        int e = 0;
-        if (m > 0.0 && m <= 1.7e308) e = ilogb(m) >> 1;   // arithmetic shift: floor for negatives too
-        *d_exp = e;
+    const double m = sh[0];
+    int e = 0;
+    if (m > 0.0 && m <= 1.7e308) e = ilogb(m) >> 1;   // arithmetic shift: floor for negatives too
+    return e;
+}
+
+__global__ __launch_bounds__(256) void k_prescale(const double2* __restrict__ A, int n, int lda, int* __restrict__ d_exp) {
+    const int e = prescale_exp_block(A, n, lda);
+    if (threadIdx.x == 0) *d_exp = e;
+}
+
+// One workgroup per matrix of a same-size group: the dense padded copy of an
+// odd-n loop hafnian (isolated vertex of loop weight 1, as the pad kernel
+// builds it), and the exponent from the caller's matrix (padding adds only
+// zeros off the diagonal, so the exponent is that of the padded matrix).
+__global__ __launch_bounds__(256) void k_group_prologue(const GroupItem* __restrict__ items, int* __restrict__ exps) {
+    const GroupItem it = items[blockIdx.x];
+    if (it.A != it.src) {
+        double2* dst = const_cast<double2*>(it.A);
+        for (int e = threadIdx.x; e < it.n * it.n; e += 256) {
+            const int i = e / it.n, j = e % it.n;
+            double2 v = cz();
+            if (i < it.src_n && j < it.src_n) v = it.src[(int64_t)i * it.src_lda + j];
+            else if (i == it.src_n && j == it.src_n) v = cone();
+            dst[(int64_t)i * it.lda + j] = v;
+        }
     }
+    const int e = prescale_exp_block(it.src, it.src_n, it.src_lda);
+    if (threadIdx.x == 0) exps[blockIdx.x] = e;
 }
 
 __global__ void k_scatter(const double2* __restrict__ in, const int* __restrict__ perm, int count,
@@ -251,6 +328,19 @@ hipError_t launch_prescale(hipStream_t st, const double2* A, int n, int lda, int
 
 hipError_t launch_write_const(hipStream_t st, double re, double* out_dd, double2* out) {
     hipLaunchKernelGGL(k_write_const, dim3(1), dim3(64), 0, st, re, out_dd, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_prologue(hipStream_t st, const GroupItem* items, int nitems, int* exps) {
+    if (nitems < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_group_prologue, dim3(nitems), dim3(256), 0, st, items, exps);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_group(hipStream_t st, const GroupItem* items, int nitems, const double* partials,
+                               const int* exps, int N) {
+    if (nitems < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_group, dim3(nitems), dim3(256), 0, st, items, partials, exps, N);
     return hipGetLastError();
 }
 

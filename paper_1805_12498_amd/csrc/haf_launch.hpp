@@ -51,6 +51,43 @@ int reg_layout_index(int s);
 hipError_t launch_series_multi(int N, bool loops, hipStream_t st, const double2* coef, double* partials,
                                MultiChunks mc);
 
+// Same-size matrices of a batch in shared launches.  Matrix j of a group is
+// items[j]; chunk c of a launch covers subsets 0..count-1 of size class m of
+// matrix `item` (N <= 16: one chunk per class), owns the workgroups gstart ..
+// (next chunk's gstart or the grid) - 1, keeps its coefficients at coef + coff
+// (stride count) and, for the series, writes partial slots slot, slot + 1, ...
+// Every matrix's coefficients, partial slots and reduction are those of the
+// single-matrix path, so its result is bitwise the same.
+struct GroupItem {
+    const double2* A;                    // matrix the kernels read (the dense copy for odd-n loop hafnians)
+    const double2* src;                  // caller's matrix; the prologue pads it into A when they differ
+    double2* out;                        // result
+    int n, lda, src_n, src_lda;
+    int64_t slot_base;                   // the matrix's first partial slot
+    int64_t nslots;                      // its partial slots
+};
+struct GroupChunk {
+    int item, m, count, gstart;
+    int64_t coff, slot;
+    double sign;                         // (-1)^(N - m)
+};
+// One workgroup per matrix: pad odd-n loop hafnians into A, exponent of the
+// exact input scaling into exps[j] (as the prescale kernel computes it).
+hipError_t launch_group_prologue(hipStream_t st, const GroupItem* items, int nitems, int* exps);
+// Coefficients of the chunks of one launch (all s = 2m in the range of the
+// default layout named by s_max); blocks = the launch's grid, as planned by the
+// host with group_coef_blocks.
+int group_coef_blocks(int s_max, int count);
+hipError_t launch_coef_reg_group(int s_max, bool loops, int blocks, hipStream_t st, const GroupItem* items,
+                                 const GroupChunk* chunks, int nchunks, int N, const int* exps, double2* coef);
+// Series + signed block partials of the chunks of one launch (N <= 16).
+int group_series_blocks(int count);
+hipError_t launch_series_group(int N, bool loops, int blocks, hipStream_t st, const GroupChunk* chunks, int nchunks,
+                               const double2* coef, double* partials);
+// One workgroup per matrix: its partials reduced as the single-matrix path does.
+hipError_t launch_reduce_group(hipStream_t st, const GroupItem* items, int nitems, const double* partials,
+                               const int* exps, int N);
+
 // Exponent e of the exact input scaling (off-diagonal by 2^-2e, diagonal by
 // 2^-e; the result is multiplied back by 2^(2eN)), written to *d_exp.
 hipError_t launch_prescale(hipStream_t st, const double2* A, int n, int lda, int* d_exp);

@@ -148,6 +148,34 @@ def test_errors(hg):
     hg.batched_dev(dA.data_ptr(), [], [], [], out.data_ptr(), st)      # empty batch: nothing to do
 
 
+def test_grouped_vs_ungrouped_bitwise(hg):
+    """Same-size matrices in shared launches (grouped, the default) against every matrix
+    on its own launches: bitwise equal, over constants, odd n, padded odd-n loop hafnians,
+    sizes past the grouped range (n > 32) and a group of n = 32 loop hafnians large enough
+    to be split into two coefficient sub-batches."""
+    mats, kinds = [], []
+    for n in list(range(0, 34)) + [36, 40]:
+        for kind in (0, 1):
+            mats.append(rand_sym(n, 5000 + 2 * n + kind))
+            kinds.append(kind)
+    for t in range(9):
+        mats.append(rand_sym(32, 6000 + t))
+        kinds.append(1)
+    mats.append(rand_sym(31, 6100))
+    kinds.append(1)
+    try:
+        hg.set_batched_config(streams=4, grouped=1)
+        g = run_batch(hg, mats, kinds)
+        hg.set_batched_config(streams=4, grouped=0)
+        u = run_batch(hg, mats, kinds)
+    finally:
+        hg.set_batched_config(streams=8)
+    for t in range(len(mats)):
+        assert g[t] == u[t], (t, mats[t].shape[0], kinds[t], g[t], u[t])
+    for t in (0, 5, 17, 40, 60, 71):
+        assert g[t] == run_plain(hg, mats[t], kinds[t]), (t, mats[t].shape[0])
+
+
 def test_autotuner(hg):
     import torch
     mats = gi.gbs_batch(64, seed=10)
@@ -159,6 +187,7 @@ def test_autotuner(hg):
                               torch.cuda.current_stream().cuda_stream)
     print("tuned:", cfg, "%.3f ms" % ms, flush=True)
     assert hg.batched_config() == cfg and ms > 0 and cfg["streams"] in (1, 2, 4, 8, 16)
+    assert cfg["grouped"] in (0, 1)
     tuned = out.cpu().numpy()
     again = run_batch(hg, mats, kinds)
     assert np.array_equal(tuned, again)
