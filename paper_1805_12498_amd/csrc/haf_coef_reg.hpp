@@ -275,6 +275,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             double lx = group_sum<L>(prod.x), ly = group_sum<L>(prod.y);
             if (valid && lam == 0) coef[(int64_t)N * cstride + sub] = make_double2(lx, ly);
             for (int k = 2; k <= N; ++k) {
+                __builtin_amdgcn_s_setprio(0);
 #pragma unroll
                 for (int t = 0; t < R; ++t) {
                     double2 acc = cz();
@@ -282,6 +283,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                     for (int u = 0; u < C; ++u) cfma(acc, h[t][u], yc[u]);
                     ypart[a + P * t + S::YB * b] = acc;
                 }
+                __builtin_amdgcn_s_setprio(2);    // sums, moment and broadcast: the serial part
                 __syncthreads();
                 double2 yr = cz();            // (B y)_lam
                 if (lam < s) yr = tree_sum<Q, S::YB>(ypart + lam);
@@ -295,6 +297,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
 #pragma unroll
                 for (int u = 0; u < C; ++u) yc[u] = (b + Q * u < s) ? yb[b + Q * u] : cz();
             }
+            __builtin_amdgcn_s_setprio(0);
         }
 
         if constexpr (ELIM) {
