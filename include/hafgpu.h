@@ -117,13 +117,18 @@ int haf_terms_dev(const haf_cplx* dA, int n, int lda, int kind, const uint32_t* 
  * after everything already on `stream`, and `stream` does not pass the call
  * until every result is written.
  *
- * The matrices are spread, largest model cost first, over a pool of
- * library-owned streams (haf_batched_config.streams of them), each filled by
- * its own host thread with the single-matrix path, so that the kernels of
- * different matrices overlap on the device.  Every result is therefore
- * bitwise the single-matrix path's result for that matrix, whatever else is in
- * the batch.  (The library also holds a persistent kernel that runs a whole
- * batch from one work counter; that path is switched off in this build.)
+ * With haf_batched_config.grouped = 1 (default) the matrices with n <= 32
+ * (after padding odd-n loop hafnians) run in shared launches per (n, kind) on
+ * the first of a pool of library-owned streams: one launch per layout for the
+ * coefficients of all their subset sizes, one for the series, one reduction.
+ * The rest (and, with grouped = 0, every matrix) is spread, largest model cost
+ * first, over the pool (haf_batched_config.streams streams), each filled by its
+ * own host thread with the single-matrix path.  Either way each matrix keeps
+ * the single-matrix path's per-subset arithmetic, partial slots and reduction
+ * order, so every result is bitwise the single-matrix path's result for that
+ * matrix, whatever else is in the batch.  (The library also holds a persistent
+ * kernel that runs a whole batch from one work counter; that path is switched
+ * off in this build.)
  * Errors: HAF_E_INVALID_ARG (null pointer, count < 0, n_t < 0, unknown kind),
  * HAF_E_TOO_LARGE (n_t > HAF_MAX_N), HAF_E_NOMEM, HAF_E_DEVICE.  Matrices are
  * not checked for symmetry (they live in device memory).
