@@ -41,11 +41,11 @@ _RECORDS = []
 
 
 def record(what, err, kappa):
-    """Keep measured relative errors; written to gpurun_out/parity_errors.json when that folder exists."""
+    """Keep measured relative errors; written as JSON to the file HAFGPU_PARITY_LOG names, if set."""
     _RECORDS.append({"case": what, "relerr": err, "kappa": kappa, "relerr_over_eps_kappa": err / (EPS * kappa)})
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(out):
-        with open(os.path.join(out, "parity_errors.json"), "w") as f:
+    out = os.environ.get("HAFGPU_PARITY_LOG")
+    if out:
+        with open(out, "w") as f:
             json.dump(_RECORDS, f, indent=1)
 
 
