@@ -86,6 +86,19 @@ int lhaf_c128(const haf_cplx* A, int n, int lda, haf_cplx* out);
 int haf_c128x2_host(const haf_cplx* A, int n, int lda, int kind, haf_cplx2* out);
 
 /*
+ * perm(W) of an n x n complex matrix through the bipartite identity
+ * (Sec. 1.1): perm(W) = haf(B) for the 2n x 2n matrix B = [[0, W], [W^T, 0]]
+ * of the complete bipartite graph with edge weights W.  Host pointers,
+ * synchronous; W is read row-major with leading dimension ldw >= n and must be
+ * finite.  n = 0 gives 1; n <= 32 (HAF_E_TOO_LARGE above).  The result is the
+ * hafnian path's result for B, bit for bit.
+ */
+int perm_c128(const haf_cplx* W, int n, int ldw, haf_cplx* out);
+/* Device variant: dW is a device matrix (not inspected), d_out a device
+ * haf_cplx; B is built on `stream` in the library's workspace for that stream. */
+int perm_c128_dev(const haf_cplx* dW, int n, int ldw, haf_cplx* d_out, void* stream);
+
+/*
  * Device variants: dA is a device matrix, d_out a device haf_cplx (or
  * haf_cplx2 for the x2 form).  Only n, lda and the pointers are checked; the
  * matrix contents are not inspected (they are on the device), so the caller

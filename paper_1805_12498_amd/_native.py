@@ -28,7 +28,7 @@ EXPORTS = (
     "haf_release_workspaces", "haf_set_kernel_path", "haf_server_default_config", "haf_server_create",
     "haf_server_submit", "haf_server_poll", "haf_server_drain", "haf_server_destroy", "haf_now",
     "haf_profile_enable", "haf_profile_read", "haf_batched_get_config", "haf_batched_set_config",
-    "haf_batched_tune", "haf_batched_plan",
+    "haf_batched_tune", "haf_batched_plan", "perm_c128", "perm_c128_dev",
 )
 
 
@@ -117,6 +117,8 @@ def load(path: str = LIB_PATH):
         "haf_batched_set_config": ([vp], i),
         "haf_batched_tune": ([vp, vp, vp, vp, i, vp, vp, vp, ctypes.POINTER(ctypes.c_double)], i),
         "haf_batched_plan": ([vp, vp, i, vp, i, ctypes.POINTER(i), ctypes.POINTER(i64), ctypes.POINTER(i)], i),
+        "perm_c128": ([vp, i, i, vp], i),
+        "perm_c128_dev": ([vp, i, i, vp, vp], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -152,6 +154,21 @@ def haf_host(A, kind: int = KIND_HAF, x2: bool = False):
     fn = lib.haf_c128 if kind == KIND_HAF else lib.lhaf_c128
     check(fn(ctypes.c_void_p(ptr), n, max(n, 1), ctypes.byref(out)))
     return complex(out.re, out.im)
+
+
+def perm_host(W) -> complex:
+    """perm(W) of a host square matrix through the bipartite identity (synchronous)."""
+    W = _host_matrix(W)
+    n = W.shape[0]
+    ptr = W.ctypes.data if n else ctypes.addressof(ctypes.c_double(0.0))
+    out = c128()
+    check(load().perm_c128(ctypes.c_void_p(ptr), n, max(n, 1), ctypes.byref(out)))
+    return complex(out.re, out.im)
+
+
+def perm_dev(dW_ptr: int, n: int, ldw: int, d_out_ptr: int, stream: int = 0):
+    """Enqueue perm(W) of a device matrix; raw device pointers and a hipStream_t value."""
+    check(load().perm_c128_dev(ctypes.c_void_p(dW_ptr), n, ldw, ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(stream)))
 
 
 def haf_dev(dA_ptr: int, n: int, lda: int, d_out_ptr: int, stream: int = 0, kind: int = KIND_HAF, x2: bool = False):

@@ -281,6 +281,19 @@ __global__ void k_pad_odd(const double2* __restrict__ A, int n, int lda, double2
     }
 }
 
+// The matrix of the complete bipartite graph K_{n,n} with edge weights W: its
+// hafnian is perm(W) (the bipartite identity of Sec. 1.1).
+__global__ void k_bipartite(const double2* __restrict__ W, int n, int ldw, double2* __restrict__ B) {
+    const int m = 2 * n;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m * m; e += gridDim.x * blockDim.x) {
+        const int i = e / m, j = e % m;
+        double2 v = cz();
+        if (i < n && j >= n) v = W[(int64_t)i * ldw + (j - n)];
+        else if (i >= n && j < n) v = W[(int64_t)j * ldw + (i - n)];
+        B[e] = v;
+    }
+}
+
 }  // namespace hafgpu
 
 namespace hafgpu {
@@ -341,6 +354,13 @@ hipError_t launch_reduce_group(hipStream_t st, const GroupItem* items, int nitem
                                const int* exps, int N) {
     if (nitems < 1) return hipSuccess;
     hipLaunchKernelGGL(k_reduce_group, dim3(nitems), dim3(256), 0, st, items, partials, exps, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_bipartite(hipStream_t st, const double2* W, int n, int ldw, double2* B) {
+    const int m = 2 * n;
+    const int blocks = (m * m + 255) / 256;
+    hipLaunchKernelGGL(k_bipartite, dim3(blocks), dim3(256), 0, st, W, n, ldw, B);
     return hipGetLastError();
 }
 

@@ -103,6 +103,8 @@ hipError_t launch_reduce(hipStream_t st, const double* partials, int64_t nslots,
 hipError_t launch_scatter(hipStream_t st, const double2* in, const int* perm, int count, double2* out);
 hipError_t launch_write_const(hipStream_t st, double re, double* out_dd, double2* out);
 hipError_t launch_pad_odd(hipStream_t st, const double2* A, int n, int lda, double2* out);
+// B = [[0, W], [W^T, 0]] (2n x 2n, dense) from the n x n matrix W (leading dimension ldw).
+hipError_t launch_bipartite(hipStream_t st, const double2* W, int n, int ldw, double2* B);
 
 }  // namespace hafgpu
 

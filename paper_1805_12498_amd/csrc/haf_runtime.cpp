@@ -189,6 +189,7 @@ int release_workspaces() {
             if (w->aux) (void)hipFree(w->aux);
             if (w->pad) (void)hipFree(w->pad);
             if (w->in) (void)hipFree(w->in);
+            if (w->emb) (void)hipFree(w->emb);
             delete w;
         }
         ds->ws.clear();
@@ -577,6 +578,49 @@ int lhaf_c128_dev(const haf_cplx* dA, int n, int lda, haf_cplx* d_out, void* str
 
 int haf_c128x2_dev(const haf_cplx* dA, int n, int lda, int kind, haf_cplx2* d_out, void* stream) {
     return dev_entry(dA, n, lda, kind, (double*)d_out, nullptr, stream);
+}
+
+int perm_c128(const haf_cplx* W, int n, int ldw, haf_cplx* out) {
+    clear_error();
+    if (!W || !out) return set_error(HAF_E_INVALID_ARG, "null pointer");
+    if (n < 0) return set_error(HAF_E_INVALID_ARG, "n = %d < 0", n);
+    if (n > 0 && ldw < n) return set_error(HAF_E_INVALID_ARG, "ldw = %d < n = %d", ldw, n);
+    if (2 * n > HAF_MAX_N) return set_error(HAF_E_TOO_LARGE, "n = %d exceeds the limit %d", n, HAF_MAX_N / 2);
+    const int m = 2 * n;
+    std::vector<haf_cplx> B((size_t)std::max(m, 1) * std::max(m, 1), haf_cplx{ 0.0, 0.0 });
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const haf_cplx w = W[(int64_t)i * ldw + j];
+            if (!std::isfinite(w.re) || !std::isfinite(w.im))
+                return set_error(HAF_E_NONFINITE, "non-finite entry at (%d, %d)", i, j);
+            B[(size_t)i * m + (n + j)] = w;
+            B[(size_t)(n + j) * m + i] = w;
+        }
+    haf_cplx2 r;
+    const int rc = run_host(B.data(), m, std::max(m, 1), HAF_KIND_HAF, &r);
+    if (rc) return rc;
+    out->re = r.re_hi + r.re_lo;
+    out->im = r.im_hi + r.im_lo;
+    return HAF_OK;
+}
+
+int perm_c128_dev(const haf_cplx* dW, int n, int ldw, haf_cplx* d_out, void* stream) {
+    clear_error();
+    if (!dW || !d_out) return set_error(HAF_E_INVALID_ARG, "null pointer");
+    if (n < 0) return set_error(HAF_E_INVALID_ARG, "n = %d < 0", n);
+    if (n > 0 && ldw < n) return set_error(HAF_E_INVALID_ARG, "ldw = %d < n = %d", ldw, n);
+    if (2 * n > HAF_MAX_N) return set_error(HAF_E_TOO_LARGE, "n = %d exceeds the limit %d", n, HAF_MAX_N / 2);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = ensure_device(nullptr);
+    if (rc) return rc;
+    if (n == 0) return hip_check(launch_write_const(st, 1.0, nullptr, (double2*)d_out), "write kernel launch");
+    Workspace* w = nullptr;
+    if ((rc = workspace_for(st, &w))) return rc;
+    const int m = 2 * n;
+    if ((rc = grow((void**)&w->emb, &w->emb_cap, sizeof(double2) * (size_t)m * m, st))) return rc;
+    if ((rc = hip_check(launch_bipartite(st, (const double2*)dW, n, ldw, w->emb), "bipartite kernel launch")))
+        return rc;
+    return run_dev(w->emb, m, m, HAF_KIND_HAF, nullptr, (double2*)d_out, st);
 }
 
 int haf_terms_dev(const haf_cplx* dA, int n, int lda, int kind, const uint32_t* d_masks, int count,

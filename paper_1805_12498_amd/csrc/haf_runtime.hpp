@@ -32,6 +32,7 @@ struct Workspace {
     void* aux = nullptr; size_t aux_cap = 0;        // small scratch
     double2* pad = nullptr; size_t pad_cap = 0;     // padded odd-n matrix
     void* in = nullptr; size_t in_cap = 0;          // uploaded host matrix + result
+    double2* emb = nullptr; size_t emb_cap = 0;     // bipartite embedding of a permanent's matrix
 };
 
 int set_error(int code, const char* fmt, ...);

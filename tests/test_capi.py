@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_1805_12498_amd", "libhafgpu.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(haf\w*|lhaf\w*)\s*\(", text, flags=re.M)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(haf\w*|lhaf\w*|perm\w*)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
