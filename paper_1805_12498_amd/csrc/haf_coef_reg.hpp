@@ -651,10 +651,11 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
 
 // Layouts and the subset sizes each one serves: (P, Q, R, C, CP) for s in (lo, hi].
 // The "narrow" table packs two or four matrices per wave where the tile fits, in
-// steps of 4 rows up to 32 so that little of a tile is padding;
+// steps of 4 rows from 8 up to 32 so that little of a tile is padding;
 // the "wide" table gives every matrix above s = 16 a full wave (smaller tiles,
 // fewer registers, more resident waves).
-#define HAF_REG_NARROW(X) X(4, 4, 2, 2, 0, 0, 8) X(4, 4, 4, 4, 0, 8, 16) X(8, 4, 3, 5, 0, 16, 20) \
+#define HAF_REG_NARROW(X) X(4, 4, 2, 2, 0, 0, 8) X(4, 4, 3, 3, 0, 8, 12) X(4, 4, 4, 4, 0, 12, 16)       \
+                          X(8, 4, 3, 5, 0, 16, 20) \
                           X(8, 4, 3, 6, 0, 20, 24) X(8, 4, 4, 7, 1, 24, 28) X(8, 4, 4, 8, 1, 28, 32)      \
                           X(8, 8, 5, 5, 2, 32, 40) X(8, 8, 6, 6, 2, 40, 48)
 #define HAF_REG_WIDE(X) X(8, 8, 3, 3, 2, 16, 24) X(8, 8, 4, 4, 2, 24, 32)
