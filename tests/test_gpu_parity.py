@@ -327,6 +327,34 @@ def test_n56_sampled_terms_vs_oracle(hg):
     record("n=56 sampled terms, worst", worst, 1.0)
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_max_size_sampled_terms_vs_oracle(hg, kind):
+    """The largest size the library takes, n = 64 (N = 32: 32-bit subset masks, the series'
+    largest instance, subsets up to 64 rows on the LDS kernel): f(Z) for subsets of every
+    size class against the oracle's explicit-power terms in double-double."""
+    import torch
+    n = 64
+    A = gi.gaussian_symmetric(n, 6400 + kind)
+    rng = np.random.default_rng(64 + kind)
+    masks = [(1 << 32) - 1, 1, 1 << 31]
+    for m in (2, 7, 12, 16, 20, 24, 25, 28, 31):
+        masks.append(int(sum(1 << int(b) for b in rng.choice(32, m, replace=False))))
+    masks = np.array(sorted(set(masks)), dtype=np.uint32)
+    dA = torch.from_numpy(A).cuda()
+    dm = torch.from_numpy(masks.view(np.int32)).cuda()
+    dt = torch.zeros(len(masks), dtype=torch.complex128, device="cuda")
+    hg.terms_dev(dA.data_ptr(), n, n, kind, dm.data_ptr(), len(masks), dt.data_ptr(), 0)
+    torch.cuda.synchronize()
+    got = dt.cpu().numpy()
+    worst = 0.0
+    for g, m in zip(got, masks):
+        ref = oracle.term(A, int(m), bool(kind), prec="dd")
+        e = ref.relerr(g)
+        worst = max(worst, e)
+        assert e < 1e-9, (bin(int(m)).count("1"), kind, e)
+    record("n=64 sampled terms kind=%d, worst" % kind, worst, 1.0)
+
+
 def test_n56_graph_sampled_terms_exact(hg):
     """The 56-vertex 0/1 graph (edge probability 1/2, seed 5602): each f(Z) counts tangles
     (Sec. 3.2), an integer, computed exactly by the oracle modulo six primes and
