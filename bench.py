@@ -41,7 +41,7 @@ PEAK_FP64_TFLOPS = 78.6          # MI355X vector FP64: 256 CU x 128 flop/clk x 2
 TRAFFIC_SOURCES = ("paper_1805_12498_amd/csrc/haf_coef_reg.hpp", "paper_1805_12498_amd/csrc/haf_kernels_reg.hip",
                    "paper_1805_12498_amd/csrc/haf_common.hpp")
 TRAFFIC_SHA256 = "2b87cef18583b1ffd60e1e7a917978546d5537b3017c48513a1412d03a0d89cc"
-TRAFFIC_N56_HAF_BYTES_PER_LAUNCH = 8.830e8
+TRAFFIC_N56_HAF_BYTES_PER_LAUNCH = 8.826e8
 
 
 def coef_traffic(n, kind):
