@@ -9,7 +9,8 @@
 // followed by the copy of the result into a pinned host slot and an event.
 // Requests admitted while others run overlap with them on the device; a
 // request's result does not depend on what else runs (the single-matrix path
-// is deterministic).  Completions are found by polling the events; the result
+// is deterministic).  Completions are found by polling the events, only the
+// oldest unfinished request of each stream (a stream finishes in order); the result
 // carries the host steady-clock times of submit, admission and completion.
 // With continuous = 0 the server admits one request at a time on one stream,
 // in arrival order (the plain server).
@@ -103,7 +104,10 @@ struct haf_server {
     std::vector<hipStream_t> streams;
     std::vector<int> stream_load;
     std::vector<hipEvent_t> events;
-    std::vector<Request*> active;
+    // admitted requests per stream, in launch order: a stream completes them in
+    // that order, so only the front of each queue needs polling
+    std::vector<std::deque<Request*>> inflight;
+    int n_active = 0;
     std::string start_error;
     bool started = false;
     std::condition_variable cv_start;
@@ -176,6 +180,7 @@ void scheduler(haf_server* s) {
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail_start("stream creation failed");
         s->streams.push_back(st);
         s->stream_load.push_back(0);
+        s->inflight.emplace_back();
     }
     for (int i = 0; i < c.max_active; ++i) {
         hipEvent_t e = nullptr;
@@ -196,8 +201,8 @@ void scheduler(haf_server* s) {
             {
                 std::lock_guard<std::mutex> lk(s->mu);
                 if (s->stop || s->queue.empty()) break;
-                if ((int)s->active.size() >= c.max_active || s->free_slots.empty()) break;
-                if (!c.continuous && !s->active.empty()) break;
+                if (s->n_active >= c.max_active || s->free_slots.empty()) break;
+                if (!c.continuous && s->n_active > 0) break;
                 r = s->queue.front();
                 const int64_t off = s->alloc.alloc(r->bytes);
                 if (off < 0) break;
@@ -213,24 +218,27 @@ void scheduler(haf_server* s) {
             if (rc) {
                 finish(s, r, rc, nullptr);
             } else {
-                s->active.push_back(r);
+                s->inflight[r->stream].push_back(r);
+                s->n_active++;
             }
             progress = true;
         }
-        // ---- completions
-        for (size_t i = 0; i < s->active.size();) {
-            Request* r = s->active[i];
-            const hipError_t q = hipEventQuery(r->ev);
-            if (q == hipErrorNotReady) { ++i; continue; }
-            s->active[i] = s->active.back();
-            s->active.pop_back();
-            if (q == hipSuccess) finish(s, r, HAF_OK, s->pinned + 4 * r->slot);
-            else finish(s, r, HAF_E_DEVICE, nullptr);
-            progress = true;
+        // ---- completions, in launch order per stream
+        for (std::deque<Request*>& q : s->inflight) {
+            while (!q.empty()) {
+                Request* r = q.front();
+                const hipError_t e = hipEventQuery(r->ev);
+                if (e == hipErrorNotReady) break;
+                q.pop_front();
+                s->n_active--;
+                if (e == hipSuccess) finish(s, r, HAF_OK, s->pinned + 4 * r->slot);
+                else finish(s, r, HAF_E_DEVICE, nullptr);
+                progress = true;
+            }
         }
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            if (s->stop && s->active.empty()) break;
+            if (s->stop && s->n_active == 0) break;
         }
         if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
@@ -344,10 +352,11 @@ void haf_server_destroy(haf_server* s) {
         (void)hipStreamDestroy(st);
     }
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
-    for (Request* r : s->active) {
-        if (r->ev) (void)hipEventDestroy(r->ev);
-        delete r;
-    }
+    for (std::deque<Request*>& q : s->inflight)
+        for (Request* r : q) {
+            if (r->ev) (void)hipEventDestroy(r->ev);
+            delete r;
+        }
     if (s->arena) (void)hipFree(s->arena);
     if (s->pinned) (void)hipHostFree(s->pinned);
     for (Request* r : s->queue) delete r;
