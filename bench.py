@@ -187,8 +187,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(each GPU would own a share of the subset ranks; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              "(each GPU would own a share of the subset ranks)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -141,7 +141,7 @@ int haf_terms_dev(const haf_cplx* dA, int n, int lda, int kind, const uint32_t* 
  * order, so every result is bitwise the single-matrix path's result for that
  * matrix, whatever else is in the batch.  (The library also holds a persistent
  * kernel that runs a whole batch from one work counter; that path is switched
- * off in this build.)
+ * off.)
  * Errors: HAF_E_INVALID_ARG (null pointer, count < 0, n_t < 0, unknown kind),
  * HAF_E_TOO_LARGE (n_t > HAF_MAX_N), HAF_E_NOMEM, HAF_E_DEVICE.  Matrices are
  * not checked for symmetry (they live in device memory).

@@ -18,7 +18,7 @@ Routes (see ``haf_oracle.c`` for the arithmetic):
                         (each f(Z) counts tangles, Sec. 3.2, so it is an integer);
 * ``ryser``          -- permanents, for the bipartite identity (Sec. 1.1).
 
-Readings of the paper that this oracle fixes (each also listed in the design doc):
+Readings of the paper that this oracle fixes:
 the loop term is d^T B^(k-1) (X d) with B built from the zero-diagonal matrix
 (the printed v (XB)^(k-1) v^T fails already at n = 2); pairs are (2i, 2i+1),
 i = 0..n/2-1; n = 0 gives 1; odd n gives haf = 0 and lhaf through padding

@@ -243,7 +243,7 @@ int run_batched_persistent(const double2* dA, const int64_t* offs, const int32_t
     int rc = check_batch_args(dA, offs, ns, kinds, count, d_out);
     if (rc || count == 0) return rc;
     if (!kPersistentBatchedEnabled)
-        return set_error(HAF_E_STATE, "the persistent batched kernel is switched off in this build");
+        return set_error(HAF_E_STATE, "the persistent batched kernel is switched off");
     int dev = 0;
     if ((rc = ensure_device(&dev))) return rc;
     BatchWS* w = nullptr;
