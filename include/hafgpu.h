@@ -125,83 +125,85 @@ int haf_terms_dev(const haf_cplx* dA, int n, int lda, int kind, const uint32_t* 
  * per-matrix sums of Sec. 3.2, Eq. Pset; the paper names batched small-matrix
  * GPU work as the way forward in its conclusions).  Matrix t is stored densely
  * (lda = n_t) at element offset h_offsets[t] of dA_packed (device memory).
- * h_offsets, h_n and h_kind (HAF_KIND_*) are host arrays; d_out is a device
- * haf_cplx[count].  Asynchronous like the *_dev calls: the work is ordered
+ * h_offsets, h_n and h_kind (HAF_KIND_*) are host arrays (the plan is built on
+ * the host from the sizes alone); d_out is a device haf_cplx[count] (haf_cplx2
+ * for the x2 form).  Asynchronous like the *_dev calls: the work is ordered
  * after everything already on `stream`, and `stream` does not pass the call
  * until every result is written.
  *
- * With haf_batched_config.grouped = 1 (default) the matrices with n <= 32
- * (after padding odd-n loop hafnians) run in shared launches per (n, kind) on
- * the first of a pool of library-owned streams: one launch per layout for the
- * coefficients of all their subset sizes, one for the series, one reduction.
- * The rest (and, with grouped = 0, every matrix) is spread, largest model cost
- * first, over the pool (haf_batched_config.streams streams), each filled by its
- * own host thread with the single-matrix path.  Either way each matrix keeps
- * the single-matrix path's per-subset arithmetic, partial slots and reduction
- * order, so every result is bitwise the single-matrix path's result for that
- * matrix, whatever else is in the batch.  (The library also holds a persistent
- * kernel that runs a whole batch from one work counter; that path is switched
- * off.)
+ * With haf_batched_config.grouped = 1 (default) every matrix with n <= 32
+ * (after padding odd-n loop hafnians) runs in launches shared by the whole
+ * batch, on `stream`: one prologue (constant results, padding, input scaling),
+ * then per register layout and kind one coefficient launch over the subset
+ * size classes of every matrix that layout serves and one series launch over
+ * the same chunks, then one reduction launch.  Matrices above 32 rows (and,
+ * with grouped = 0, every matrix) run the single-matrix path spread, largest
+ * model cost first, over haf_batched_config.streams library streams.  Either
+ * way each matrix keeps the single-matrix path's per-subset arithmetic,
+ * partial slots and reduction order, so every result is bitwise the
+ * single-matrix path's result for that matrix, whatever else is in the batch
+ * and whatever the configuration.
  * Errors: HAF_E_INVALID_ARG (null pointer, count < 0, n_t < 0, unknown kind),
  * HAF_E_TOO_LARGE (n_t > HAF_MAX_N), HAF_E_NOMEM, HAF_E_DEVICE.  Matrices are
  * not checked for symmetry (they live in device memory).
  */
 int haf_batched_c128(const haf_cplx* dA_packed, const int64_t* h_offsets, const int32_t* h_n,
                      const uint8_t* h_kind, int count, haf_cplx* d_out, void* stream);
+int haf_batched_c128x2(const haf_cplx* dA_packed, const int64_t* h_offsets, const int32_t* h_n,
+                       const uint8_t* h_kind, int count, haf_cplx2* d_out, void* stream);
 
-/* Tunable parameters of the batched path (process-wide). */
+/* Tunable parameters of the batched path (process-wide).  No setting changes a result. */
 typedef struct {
-    int layout;         /* persistent kernel (switched off): 0 = several matrices per wave
-                           where the tile fits, two waves per SIMD; 1 = one full wave per
-                           matrix above 16 rows; 2 = as 0 at one wave per SIMD          */
-    int group_work;     /* persistent kernel: subsets each matrix slot of a wave takes per
-                           chunk at 16 rows, scaled by (16/s)^3 for s rows              */
-    int waves_per_cu;   /* persistent kernel: workgroups per CU, 0 = as many as fit    */
-    int streams;        /* streams the batch is spread over, 1..16 (default 8)         */
-    int grouped;        /* 1 (default): matrices with n <= 32 share launches with the other
-                           matrices of their size and kind, on the first pool stream;
-                           0: every matrix runs its own single-matrix launches           */
+    int table;          /* layouts of the shared coefficient launches: 0 (default) the
+                           single-matrix table (nine layouts), 1 four coarse layouts (fewer
+                           launches, more padded rows)                                   */
+    int span;           /* subsets each lane group takes in a shared coefficient launch,
+                           1..64 (default 4): fewer unrankings against a coarser split    */
+    int streams;        /* streams for the matrices above 32 rows, 1..4 (default 4)      */
+    int grouped;        /* 1 (default): shared launches for n <= 32; 0: single-matrix
+                           launches for every matrix                                     */
+    int coef_budget_mb; /* device memory for the coefficients of one shared launch pair,
+                           MiB, 64..262144 (default 8192); a larger stage is cut into
+                           several launch pairs                                          */
 } haf_batched_config;
 
 int haf_batched_get_config(haf_batched_config* cfg);
-/* HAF_E_INVALID_ARG for values out of range.  No setting changes a result. */
+/* HAF_E_INVALID_ARG for values out of range. */
 int haf_batched_set_config(const haf_batched_config* cfg);
 /* Autotuner: runs the given batch (same arguments as haf_batched_c128; d_out
- * receives the results) with 1, 2, 4, 8 and 16 streams, grouped and not, times each run with
- * HIP events on `stream`, makes the fastest the current configuration and
- * returns it in *best and its time in *best_ms.  Synchronous. */
+ * receives the results) under a coordinate search (span 1..16 with the full
+ * layout table, then the other table, then 1, 2, 4 streams, then grouped = 0),
+ * times each run with HIP events on `stream`, makes the fastest the current
+ * configuration and returns it in *best and its time in *best_ms.  Synchronous. */
 int haf_batched_tune(const haf_cplx* dA_packed, const int64_t* h_offsets, const int32_t* h_n,
                      const uint8_t* h_kind, int count, haf_cplx* d_out, void* stream, haf_batched_config* best,
                      double* best_ms);
-/* Host-only view of the persistent kernel's plan under the current
- * configuration (no device needed; the kernel itself is switched off).  A
- * batch runs there as two persistent launches: first the chunks of
- * subsets above 32 rows, then the rest.  classes receives, in launch order,
- * 8 int32 per class (item, m, cap, total, j0, chunk_base, slot_base, the item's
- * slot count), up to max_classes of them; chunk_base counts within its launch.
- * *n_classes, *n_chunks (both launches) and *variant (the kernel variant of
- * the second launch) are filled in. */
-int haf_batched_plan(const int32_t* h_n, const uint8_t* h_kind, int count, int32_t* classes, int max_classes,
-                     int* n_classes, int64_t* n_chunks, int* variant);
+/* Host-only view of the shared launches under the current configuration (no
+ * device needed).  launches receives 8 int64 per launch, in launch order:
+ * (what: 0 coefficients / 1 series, layout, loops, blocks, first chunk, chunks,
+ * coefficient storage in complex values, largest s of the layout); chunks
+ * receives 8 int64 per chunk: (matrix index, m, subsets, first block, coefficient
+ * offset, first partial slot, N, first rank).  Matrices that do not take the
+ * shared launches appear in neither.  At most max_launches / max_chunks
+ * entries are written; *n_launches and *n_chunks receive the full counts. */
+int haf_batched_plan(const int32_t* h_n, const uint8_t* h_kind, int count, int64_t* launches, int max_launches,
+                     int* n_launches, int64_t* chunks, int max_chunks, int* n_chunks);
 
 /* Free every cached workspace of every device (waits for the device first). */
 int haf_release_workspaces(void);
 
 /* Kernel path selection (for testing and tuning): 0 = automatic (for n <= 32
  * all size classes of a matrix go out in one coefficient launch per layout and
- * one series launch), 1 = LDS kernel only (Householder), 2 = register-tiled
- * kernels with Householder reflections, one launch pair per size class (bitwise
- * the results of 0), 3 = as 2 with one full wave per matrix above s = 16,
- * 4 = register-tiled kernels with the Hessenberg form by elimination with row
- * and column exchanges.  All reach the same characteristic polynomial (any
- * similarity does, App. B); they differ in rounding.  Process-wide. */
+ * one series launch), 1 = LDS kernel only, 2 = register-tiled kernels, one
+ * launch pair per size class (bitwise the results of 0).  All reach the same
+ * characteristic polynomial (any similarity does, App. B); 1 differs from 0
+ * and 2 in rounding.  Process-wide. */
 int haf_set_kernel_path(int path);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing.  While enabled, every coefficient launch (the per-subset
- * Hessenberg / characteristic-polynomial stage), every series launch and every
- * persistent batched launch is bracketed by HIP events recorded on the
- * launch's own stream.                                                        */
+ * Hessenberg / characteristic-polynomial stage) and every series launch is
+ * bracketed by HIP events recorded on the launch's own stream.                */
 typedef struct {
     int64_t coef_launches;      /* coefficient kernel launches                         */
     double coef_ms;             /* summed event time of those launches                 */
@@ -210,7 +212,7 @@ typedef struct {
     int64_t coef_subsets;       /* subsets they processed                              */
     int64_t series_launches;
     double series_ms;
-    int64_t batched_launches;   /* persistent batched kernel launches (also serving ticks) */
+    int64_t batched_launches;   /* coefficient launches shared by the matrices of a batch */
     double batched_ms;
     double batched_model_flops; /* same flop model over the subsets they processed      */
 } haf_profile;

@@ -28,7 +28,7 @@ EXPORTS = (
     "haf_release_workspaces", "haf_set_kernel_path", "haf_server_default_config", "haf_server_create",
     "haf_server_submit", "haf_server_poll", "haf_server_drain", "haf_server_destroy", "haf_now",
     "haf_profile_enable", "haf_profile_read", "haf_batched_get_config", "haf_batched_set_config",
-    "haf_batched_tune", "haf_batched_plan", "perm_c128", "perm_c128_dev",
+    "haf_batched_tune", "haf_batched_plan", "haf_batched_c128x2", "perm_c128", "perm_c128_dev",
 )
 
 
@@ -60,8 +60,8 @@ class Profile(ctypes.Structure):
 
 
 class BatchedConfig(ctypes.Structure):
-    _fields_ = [("layout", ctypes.c_int), ("group_work", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
-                ("streams", ctypes.c_int), ("grouped", ctypes.c_int)]
+    _fields_ = [("table", ctypes.c_int), ("span", ctypes.c_int), ("streams", ctypes.c_int), ("grouped", ctypes.c_int),
+                ("coef_budget_mb", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH):
         "haf_c128x2_dev": ([vp, i, i, i, vp, vp], i),
         "haf_terms_dev": ([vp, i, i, i, vp, i, vp, vp], i),
         "haf_batched_c128": ([vp, vp, vp, vp, i, vp, vp], i),
+        "haf_batched_c128x2": ([vp, vp, vp, vp, i, vp, vp], i),
         "haf_release_workspaces": ([], i),
         "haf_set_kernel_path": ([i], i),
         "haf_server_default_config": ([vp], None),
@@ -116,7 +117,7 @@ def load(path: str = LIB_PATH):
         "haf_batched_get_config": ([vp], i),
         "haf_batched_set_config": ([vp], i),
         "haf_batched_tune": ([vp, vp, vp, vp, i, vp, vp, vp, ctypes.POINTER(ctypes.c_double)], i),
-        "haf_batched_plan": ([vp, vp, i, vp, i, ctypes.POINTER(i), ctypes.POINTER(i64), ctypes.POINTER(i)], i),
+        "haf_batched_plan": ([vp, vp, i, vp, i, ctypes.POINTER(i), vp, i, ctypes.POINTER(i)], i),
         "perm_c128": ([vp, i, i, vp], i),
         "perm_c128_dev": ([vp, i, i, vp, vp], i),
     }
@@ -198,12 +199,14 @@ def _batch_arrays(offsets, sizes, kinds):
     return offsets, sizes, kinds
 
 
-def batched_dev(dA_ptr: int, offsets, sizes, kinds, d_out_ptr: int, stream: int = 0):
-    """Enqueue len(sizes) hafnians of matrices packed densely at element offsets of dA."""
+def batched_dev(dA_ptr: int, offsets, sizes, kinds, d_out_ptr: int, stream: int = 0, x2: bool = False):
+    """Enqueue len(sizes) hafnians of matrices packed densely at element offsets of dA
+    (x2: double-double results, 4 doubles per matrix)."""
     offsets, sizes, kinds = _batch_arrays(offsets, sizes, kinds)
-    check(load().haf_batched_c128(ctypes.c_void_p(dA_ptr), ctypes.c_void_p(offsets.ctypes.data),
-                                  ctypes.c_void_p(sizes.ctypes.data), ctypes.c_void_p(kinds.ctypes.data),
-                                  len(sizes), ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(stream)))
+    lib = load()
+    fn = lib.haf_batched_c128x2 if x2 else lib.haf_batched_c128
+    check(fn(ctypes.c_void_p(dA_ptr), ctypes.c_void_p(offsets.ctypes.data), ctypes.c_void_p(sizes.ctypes.data),
+             ctypes.c_void_p(kinds.ctypes.data), len(sizes), ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(stream)))
 
 
 def batched_config() -> dict:
@@ -212,9 +215,9 @@ def batched_config() -> dict:
     return {f: getattr(c, f) for f, _ in BatchedConfig._fields_}
 
 
-def set_batched_config(layout: int = 0, group_work: int = 16, waves_per_cu: int = 0, streams: int = 8,
-                       grouped: int = 1):
-    c = BatchedConfig(layout, group_work, waves_per_cu, streams, grouped)
+def set_batched_config(table: int = 0, span: int = 4, streams: int = 4, grouped: int = 1,
+                       coef_budget_mb: int = 8192):
+    c = BatchedConfig(table, span, streams, grouped, coef_budget_mb)
     check(load().haf_batched_set_config(ctypes.byref(c)))
 
 
@@ -231,18 +234,20 @@ def batched_tune(dA_ptr: int, offsets, sizes, kinds, d_out_ptr: int, stream: int
 
 
 def batched_plan(sizes, kinds):
-    """Host-only plan: (classes as an int32 array [n_classes, 8], n_chunks, kernel variant)."""
+    """Host-only plan of the shared batched launches under the current configuration:
+    (launches as int64 [n, 8], chunks as int64 [n, 8]); see haf_batched_plan."""
     sizes = np.ascontiguousarray(sizes, dtype=np.int32)
     kinds = np.ascontiguousarray(kinds, dtype=np.uint8)
     lib = load()
-    ncls, nch, var = ctypes.c_int(0), ctypes.c_int64(0), ctypes.c_int(0)
+    nl, nc = ctypes.c_int(0), ctypes.c_int(0)
     check(lib.haf_batched_plan(ctypes.c_void_p(sizes.ctypes.data), ctypes.c_void_p(kinds.ctypes.data), len(sizes),
-                               None, 0, ctypes.byref(ncls), ctypes.byref(nch), ctypes.byref(var)))
-    out = np.zeros((max(ncls.value, 1), 8), dtype=np.int32)
+                               None, 0, ctypes.byref(nl), None, 0, ctypes.byref(nc)))
+    launches = np.zeros((max(nl.value, 1), 8), dtype=np.int64)
+    chunks = np.zeros((max(nc.value, 1), 8), dtype=np.int64)
     check(lib.haf_batched_plan(ctypes.c_void_p(sizes.ctypes.data), ctypes.c_void_p(kinds.ctypes.data), len(sizes),
-                               ctypes.c_void_p(out.ctypes.data), ncls.value, ctypes.byref(ncls), ctypes.byref(nch),
-                               ctypes.byref(var)))
-    return out[:ncls.value], nch.value, var.value
+                               ctypes.c_void_p(launches.ctypes.data), nl.value, ctypes.byref(nl),
+                               ctypes.c_void_p(chunks.ctypes.data), nc.value, ctypes.byref(nc)))
+    return launches[:nl.value], chunks[:nc.value]
 
 
 def set_kernel_path(path: int):

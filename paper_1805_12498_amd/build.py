@@ -25,8 +25,6 @@ SOURCES = [
     "haf_kernels_lds.hip",
     "haf_kernels_reg.hip",
     "haf_kernels_series.hip",
-    "haf_kernels_batched.hip",
-    "haf_kernels_batched24.hip",
     "haf_runtime.cpp",
     "haf_batched.cpp",
     "haf_server.cpp",

@@ -1,5 +1,18 @@
-// Batched hafnians: the host planner, the per-stream workspaces, the
-// configuration and autotuner, and the C ABI of the batched path.
+// Batched hafnians: the host planner, the workspaces, the configuration and
+// autotuner, and the C ABI of the batched path.
+//
+// A batch is run as shared launches.  Every matrix with at most 32 rows (after
+// padding an odd-n loop hafnian) contributes one chunk per subset size class m
+// (Sec. 3.2, Eq. Pset: the subsets of one size share s = 2m and the sign
+// (-1)^(N-m)).  The chunks are grouped into stages, one per (register layout,
+// kind): a stage is one coefficient launch over the chunks of every matrix
+// whose subset size that layout serves, followed by one series launch over the
+// same chunks, so the coefficients of one stage are reused by the next.  One
+// reduction launch per batch then folds each matrix's partial slots.  Each
+// matrix keeps the single-matrix path's per-subset arithmetic (same layout
+// P, Q and polynomial split for every s), its partial slots and its reduction
+// order, so every result is bitwise the single-matrix result.  Matrices above
+// 32 rows run the single-matrix path on up to four library streams.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,15 +24,17 @@
 #include <thread>
 #include <vector>
 
-#include "haf_batch_plan.hpp"
 #include "haf_launch.hpp"
 #include "haf_runtime.hpp"
 
 namespace hafgpu {
 
-// ------------------------------------------------------------------ planner
+constexpr int kGroupMaxN = 32;        // largest matrix (after padding) that takes the shared launches
+constexpr int kMaxPoolStreams = 4;    // hardware queues per process on the target
+
+// ------------------------------------------------------------------ configuration
 static std::mutex g_bcfg_mu;
-static haf_batched_config g_bcfg = { 0, 16, 0, 8, 1 };
+static haf_batched_config g_bcfg = { 0, 4, kMaxPoolStreams, 1, 8192 };
 
 haf_batched_config batch_config() {
     std::lock_guard<std::mutex> lk(g_bcfg_mu);
@@ -31,129 +46,149 @@ static void set_batch_config(const haf_batched_config& c) {
     g_bcfg = c;
 }
 
-ItemShape classify_item(int n_src, int kind) {
-    ItemShape sh{ kItemComputed, n_src, n_src / 2, kind == HAF_KIND_LHAF, false };
-    if (n_src == 0) { sh.kind = kItemOne; return sh; }
-    if (n_src % 2 == 1) {
-        if (kind == HAF_KIND_HAF) { sh.kind = kItemZero; return sh; }
-        sh.n = n_src + 1;
-        sh.N = sh.n / 2;
-        sh.padded = true;
-    }
-    if (sh.n > kBatchMaxS) sh.kind = kItemExternal;
-    return sh;
+static int check_config(const haf_batched_config& c) {
+    if (c.table < 0 || c.table > 1) return set_error(HAF_E_INVALID_ARG, "table %d not 0 or 1", c.table);
+    if (c.span < 1 || c.span > 64) return set_error(HAF_E_INVALID_ARG, "span %d not in 1..64", c.span);
+    if (c.streams < 1 || c.streams > kMaxPoolStreams)
+        return set_error(HAF_E_INVALID_ARG, "streams %d not in 1..%d", c.streams, kMaxPoolStreams);
+    if (c.grouped != 0 && c.grouped != 1) return set_error(HAF_E_INVALID_ARG, "grouped %d not 0 or 1", c.grouped);
+    if (c.coef_budget_mb < 64 || c.coef_budget_mb > (1 << 18))
+        return set_error(HAF_E_INVALID_ARG, "coef_budget_mb %d not in 64..262144", c.coef_budget_mb);
+    return HAF_OK;
 }
 
-int cap_table(int layout, int s) { return s > 32 ? 2 : (layout == 1 ? 1 : 0); }
-int small_variant(int layout, int max_N) {
-    if (max_N <= 16) return layout == 1 ? 1 : (layout == 2 ? 3 : 0);
-    return layout == 1 ? 5 : (layout == 2 ? 6 : 4);
+// Layout that serves subsets of s rows under table t: the single-matrix layout
+// (t = 0) or the one with the smallest multiple of 8 rows at or above s (t = 1).
+// Both have the same P, Q and polynomial split for every s, so results agree
+// bit for bit; the coarse table has fewer stages and more padding.
+static int stage_layout(int table, int s) {
+    const int fine = reg_layout_index(s);
+    if (table == 0 || fine < 0) return fine;
+    for (int l = fine; l < reg_layout_count(); ++l)
+        if (reg_layout_sm(l) % 8 == 0) return l;
+    return fine;
 }
 
-int chunk_cap(int layout, int s, int group_work) {
-    const int W = batch_group_count(cap_table(layout, s), s);
-    if (W <= 0) return 1;
-    int64_t spg = (int64_t)group_work * 4096 / ((int64_t)s * s * s);
-    spg = std::max<int64_t>(1, std::min<int64_t>(spg, kBatchMaxCap / W));
-    return (int)spg * W;
+// ------------------------------------------------------------------ planner
+static int eff_n(int n, int kind) { return (n % 2 == 1 && kind == HAF_KIND_LHAF) ? n + 1 : n; }
+static int constant_of(int n, int kind) {
+    if (n == 0) return kGroupConstOne;
+    if (n % 2 == 1 && kind == HAF_KIND_HAF) return kGroupConstZero;
+    return kGroupComputed;
+}
+static bool groupable(int n, int kind) {
+    return constant_of(n, kind) != kGroupComputed || eff_n(n, kind) <= kGroupMaxN;
 }
 
-int item_classes(int layout, int group_work, int item, int N, std::vector<BatchClass>* out) {
-    int slot = 0;
-    for (int m = 1; m <= N; ++m) {
-        const int cap = chunk_cap(layout, 2 * m, group_work);
-        const int total = (int)binom(N, m);
-        const int chunks = (total + cap - 1) / cap;
-        if (out) out->push_back(BatchClass{ item, m, cap, total, 0, 0, slot, 0 });
-        slot += chunks;
-    }
-    return slot;
-}
+struct StageLaunch {
+    int what;            // 0 coefficients, 1 series
+    int layout;
+    bool loops;
+    int blocks;
+    size_t first;        // first chunk in GroupPlan::chunks
+    int nch;
+    int64_t coef_elems;  // complex values of coefficient storage the launch pair uses
+    double flops;        // model flops of the coefficient launch
+};
 
-static double chunk_cost(int layout, const BatchClass& c) {
-    const double s = 2.0 * c.m;
-    const int W = std::max(1, batch_group_count(cap_table(layout, 2 * c.m), 2 * c.m));
-    return (double)((c.cap + W - 1) / W) * s * s * s;
-}
+struct GroupPlan {
+    std::vector<int> order;            // caller index of group item j
+    std::vector<int> cval;             // kGroupComputed or the constant result
+    std::vector<int> n_eff;
+    std::vector<int64_t> slot_base, nslots;
+    std::vector<GroupChunk> chunks;
+    std::vector<StageLaunch> launches;
+    int64_t coef_max = 0, slots = 0, pad_elems = 0;
+};
 
-int64_t order_classes(int layout, std::vector<BatchClass>& cls, std::vector<int>& njobs) {
-    std::vector<int> idx(cls.size());
-    std::iota(idx.begin(), idx.end(), 0);
-    std::vector<double> cost(cls.size());
-    for (size_t i = 0; i < cls.size(); ++i) cost[i] = chunk_cost(layout, cls[i]);
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-        if (cost[a] != cost[b]) return cost[a] > cost[b];
-        if (cls[a].item != cls[b].item) return cls[a].item < cls[b].item;
-        return cls[a].m < cls[b].m;
-    });
-    std::vector<BatchClass> sorted;
-    std::vector<int> jobs;
-    sorted.reserve(cls.size());
-    jobs.reserve(cls.size());
-    int64_t base = 0;
-    for (int i : idx) {
-        if (njobs[i] <= 0) continue;
-        BatchClass c = cls[i];
-        c.chunk_base = (int)base;
-        base += njobs[i];
-        sorted.push_back(c);
-        jobs.push_back(njobs[i]);
+static int plan_groups(const int32_t* ns, const uint8_t* kinds, const std::vector<int>& list,
+                       const haf_batched_config& cfg, GroupPlan* gp) {
+    gp->order = list;
+    const int ni = (int)list.size();
+    gp->cval.assign((size_t)ni, kGroupComputed);
+    gp->n_eff.assign((size_t)ni, 0);
+    gp->slot_base.assign((size_t)ni, 0);
+    gp->nslots.assign((size_t)ni, 0);
+    std::vector<Plan> plans((size_t)ni);
+    for (int j = 0; j < ni; ++j) {
+        const int t = list[(size_t)j];
+        gp->cval[(size_t)j] = constant_of(ns[t], kinds[t]);
+        gp->n_eff[(size_t)j] = eff_n(ns[t], kinds[t]);
+        if (gp->cval[(size_t)j] != kGroupComputed) continue;
+        if (gp->n_eff[(size_t)j] != ns[t]) gp->pad_elems += (int64_t)gp->n_eff[(size_t)j] * gp->n_eff[(size_t)j];
+        plans[(size_t)j] = make_plan(gp->n_eff[(size_t)j], kinds[t], kChunk);
+        gp->slot_base[(size_t)j] = gp->slots;
+        gp->nslots[(size_t)j] = plans[(size_t)j].nslots;
+        gp->slots += plans[(size_t)j].nslots;
     }
-    cls.swap(sorted);
-    njobs.swap(jobs);
-    return base;
-}
-
-double class_model_flops(const BatchClass& c, int N, bool loops, int nchunks_here) {
-    const int64_t first = (int64_t)c.j0 * c.cap;
-    const int64_t last = std::min<int64_t>((int64_t)(c.j0 + nchunks_here) * c.cap, c.total);
-    return (double)(last - first) * coef_model_flops(2 * c.m, N, loops);
-}
-
-int plan_batch(const int32_t* ns, const uint8_t* kinds, int count, const haf_batched_config& cfg, BatchPlan* p) {
-    p->shapes.resize((size_t)count);
-    p->item_slots.assign((size_t)count, 0);
-    p->slot0.assign((size_t)count, 0);
-    std::vector<BatchClass> all;
-    int max_N = 1;
-    for (int t = 0; t < count; ++t) {
-        p->shapes[t] = classify_item(ns[t], kinds[t]);
-        const ItemShape& sh = p->shapes[t];
-        if (sh.kind != kItemComputed) continue;
-        max_N = std::max(max_N, sh.N);
-        if (sh.padded) p->pad_elems += (int64_t)sh.n * sh.n;
-        p->item_slots[t] = item_classes(cfg.layout, cfg.group_work, t, sh.N, &all);
-    }
-    p->variant[0] = kBigVariant;
-    p->variant[1] = small_variant(cfg.layout, max_N);
-    for (int t = 0; t < count; ++t) {
-        p->slot0[t] = p->nslots;
-        p->nslots += p->item_slots[t];
-    }
-    for (const BatchClass& c : all) {
-        const int L = 2 * c.m > 32 ? 0 : 1;
-        const int nj = (c.total + c.cap - 1) / c.cap;
-        p->cls[L].push_back(c);
-        p->njobs[L].push_back(nj);
-        p->flops[L] += class_model_flops(c, p->shapes[c.item].N, p->shapes[c.item].loops, nj);
-    }
-    for (int L = 0; L < 2; ++L) {
-        p->nchunks[L] = order_classes(cfg.layout, p->cls[L], p->njobs[L]);
-        if (p->nchunks[L] > INT32_MAX)
-            return set_error(HAF_E_TOO_LARGE, "batch too large: %lld chunks", (long long)p->nchunks[L]);
-    }
+    const int64_t budget = (int64_t)cfg.coef_budget_mb * (1 << 20) / (int64_t)sizeof(double2);
+    // stages: one per (layout, kind), larger layouts first
+    for (int loops = 0; loops < 2; ++loops)
+        for (int lay = reg_layout_count() - 1; lay >= 0; --lay) {
+            std::vector<GroupChunk> cur;
+            std::vector<int64_t> size;
+            for (int j = 0; j < ni; ++j) {
+                if (gp->cval[(size_t)j] != kGroupComputed) continue;
+                const int t = list[(size_t)j];
+                if ((kinds[t] == HAF_KIND_LHAF) != (loops == 1)) continue;
+                const Plan& p = plans[(size_t)j];
+                for (const Chunk& c : p.chunks) {
+                    if (stage_layout(cfg.table, 2 * c.m) != lay) continue;
+                    GroupChunk ch{};
+                    ch.item = j;
+                    ch.m = c.m;
+                    ch.count = c.count;
+                    ch.N = p.N;
+                    ch.rank0 = c.rank0;
+                    ch.slot = gp->slot_base[(size_t)j] + c.slot0;
+                    ch.sign = ((p.N - c.m) & 1) ? -1.0 : 1.0;
+                    cur.push_back(ch);
+                    size.push_back((int64_t)c.count * p.ncoef);
+                }
+            }
+            // cut the stage into launch pairs whose coefficients fit the budget
+            for (size_t c0 = 0; c0 < cur.size();) {
+                int64_t used = 0;
+                size_t c1 = c0;
+                while (c1 < cur.size() && (c1 == c0 || used + size[c1] <= budget)) used += size[c1++];
+                StageLaunch co{ 0, lay, loops == 1, 0, gp->chunks.size(), (int)(c1 - c0), used, 0.0 };
+                StageLaunch se{ 1, lay, loops == 1, 0, gp->chunks.size() + (c1 - c0), (int)(c1 - c0), used, 0.0 };
+                int64_t off = 0;
+                for (size_t c = c0; c < c1; ++c) {
+                    cur[c].coff = off;
+                    off += size[c];
+                }
+                for (size_t c = c0; c < c1; ++c) {
+                    GroupChunk ch = cur[c];
+                    ch.gstart = co.blocks;
+                    co.blocks += group_coef_blocks(lay, ch.count, cfg.span);
+                    co.flops += (double)ch.count * coef_model_flops(2 * ch.m, ch.N, loops == 1);
+                    gp->chunks.push_back(ch);
+                }
+                for (size_t c = c0; c < c1; ++c) {
+                    GroupChunk ch = cur[c];
+                    ch.gstart = se.blocks;
+                    se.blocks += group_series_blocks(ch.count);
+                    gp->chunks.push_back(ch);
+                }
+                gp->launches.push_back(co);
+                gp->launches.push_back(se);
+                gp->coef_max = std::max(gp->coef_max, used);
+                c0 = c1;
+            }
+        }
     return HAF_OK;
 }
 
 // ------------------------------------------------------------------ workspaces
 struct BatchWS {
-    char* dmeta = nullptr; size_t dmeta_cap = 0;   // items | classes | new-item list
+    char* dmeta = nullptr; size_t dmeta_cap = 0;   // items | chunks
     char* hmeta = nullptr; size_t hmeta_cap = 0;   // pinned staging of the same
     hipEvent_t staged = nullptr;                   // the last upload out of hmeta
     bool staged_used = false;
-    int* dstate = nullptr; size_t dstate_cap = 0;  // exponents | done counters | chunk counter
+    int* dstate = nullptr; size_t dstate_cap = 0;  // exponents
     double* part = nullptr; size_t part_cap = 0;   // partial slots
-    double2* coef = nullptr; size_t coef_cap = 0;  // per-wave coefficient scratch
+    double2* coef = nullptr; size_t coef_cap = 0;  // coefficients of one launch pair
     double2* pad = nullptr; size_t pad_cap = 0;    // padded odd-n matrices
 };
 static std::mutex g_bws_mu;
@@ -215,7 +250,6 @@ void release_batch_workspaces() {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// ------------------------------------------------------------------ one batched call
 static int check_batch_args(const void* dA, const int64_t* offs, const int32_t* ns, const uint8_t* kinds, int count,
                             const void* d_out) {
     if (count < 0) return set_error(HAF_E_INVALID_ARG, "count = %d < 0", count);
@@ -226,124 +260,90 @@ static int check_batch_args(const void* dA, const int64_t* offs, const int32_t* 
         if (kinds[t] != HAF_KIND_HAF && kinds[t] != HAF_KIND_LHAF)
             return set_error(HAF_E_INVALID_ARG, "kind[%d] = %d unknown", t, kinds[t]);
         if (offs[t] < 0) return set_error(HAF_E_INVALID_ARG, "offset[%d] < 0", t);
-        const int eff = (ns[t] % 2 == 1 && kinds[t] == HAF_KIND_LHAF) ? ns[t] + 1 : ns[t];
-        if (eff > HAF_MAX_N) return set_error(HAF_E_TOO_LARGE, "n[%d] = %d exceeds the limit %d", t, ns[t], HAF_MAX_N);
+        if (eff_n(ns[t], kinds[t]) > HAF_MAX_N)
+            return set_error(HAF_E_TOO_LARGE, "n[%d] = %d exceeds the limit %d", t, ns[t], HAF_MAX_N);
     }
     return HAF_OK;
 }
 
-// The persistent kernel path.  Switched off: its first GPU run ended in a
-// memory fault whose cause has not been found (the same plan and kernel source
-// run clean under a CPU emulation of the wave with address checking), so no
-// call reaches it until the cause is known.
-constexpr bool kPersistentBatchedEnabled = false;
-
-int run_batched_persistent(const double2* dA, const int64_t* offs, const int32_t* ns, const uint8_t* kinds,
-                           int count, double2* d_out, hipStream_t st, const haf_batched_config& cfg) {
-    int rc = check_batch_args(dA, offs, ns, kinds, count, d_out);
-    if (rc || count == 0) return rc;
-    if (!kPersistentBatchedEnabled)
-        return set_error(HAF_E_STATE, "the persistent batched kernel is switched off");
-    int dev = 0;
-    if ((rc = ensure_device(&dev))) return rc;
+// ------------------------------------------------------------------ shared launches
+static int run_grouped(const double2* dA, const int64_t* offs, const int32_t* ns, const uint8_t* kinds,
+                       const std::vector<int>& list, double2* d_out, double* d_out_dd, hipStream_t st,
+                       const haf_batched_config& cfg) {
+    if (list.empty()) return HAF_OK;
     BatchWS* w = nullptr;
-    if ((rc = batch_ws(st, &w))) return rc;
-
-    BatchPlan plan;
-    if ((rc = plan_batch(ns, kinds, count, cfg, &plan))) return rc;
-    const std::vector<ItemShape>& shapes = plan.shapes;
+    int rc = batch_ws(st, &w);
+    if (rc) return rc;
+    GroupPlan gp;
+    if ((rc = plan_groups(ns, kinds, list, cfg, &gp))) return rc;
+    const int ni = (int)list.size();
 
     // device buffers
-    const size_t ncls = plan.cls[0].size() + plan.cls[1].size();
-    const size_t items_b = align256(sizeof(BatchItem) * count);
-    const size_t cls_b = align256(sizeof(BatchClass) * std::max<size_t>(ncls, 1));
-    const size_t new_b = align256(sizeof(int) * count);
-    const size_t meta_b = items_b + cls_b + new_b;
-    int grid[2] = { 0, 0 };
-    for (int L = 0; L < 2; ++L) {
-        const int wpc = cfg.waves_per_cu > 0 ? cfg.waves_per_cu : batch_waves_per_cu(plan.variant[L]);
-        grid[L] = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)device_cus(dev) * wpc, plan.nchunks[L]));
-    }
-    const int grid_max = std::max(grid[0], grid[1]);
+    if (gp.pad_elems &&
+        (rc = grow((void**)&w->pad, &w->pad_cap, sizeof(double2) * (size_t)gp.pad_elems, st)))
+        return rc;
+    if ((rc = grow((void**)&w->coef, &w->coef_cap, sizeof(double2) * (size_t)std::max<int64_t>(gp.coef_max, 1), st)))
+        return rc;
+    if ((rc = grow((void**)&w->part, &w->part_cap, sizeof(double) * 4 * (size_t)std::max<int64_t>(gp.slots, 1), st)))
+        return rc;
+    if ((rc = grow((void**)&w->dstate, &w->dstate_cap, sizeof(int) * (size_t)ni, st))) return rc;
+    const size_t items_b = align256(sizeof(GroupItem) * (size_t)ni);
+    const size_t meta_b = items_b + align256(sizeof(GroupChunk) * std::max<size_t>(gp.chunks.size(), 1));
     if ((rc = grow((void**)&w->dmeta, &w->dmeta_cap, meta_b, st))) return rc;
-    if ((rc = grow_pinned(w, meta_b))) return rc;
-    if ((rc = grow((void**)&w->dstate, &w->dstate_cap, sizeof(int) * (2 * (size_t)count + 64), st))) return rc;
-    if ((rc = grow((void**)&w->part, &w->part_cap, sizeof(double) * 4 * (size_t)std::max<int64_t>(plan.nslots, 1),
-                   st)))
-        return rc;
-    if ((rc = grow((void**)&w->coef, &w->coef_cap,
-                   sizeof(double2) * (size_t)grid_max *
-                       std::max(batch_coef_per_wave(plan.variant[0]), batch_coef_per_wave(plan.variant[1])),
-                   st)))
-        return rc;
-    if (plan.pad_elems &&
-        (rc = grow((void**)&w->pad, &w->pad_cap, sizeof(double2) * (size_t)plan.pad_elems, st)))
-        return rc;
-
-    // host staging (wait until the previous upload out of it has been consumed)
     if (w->staged_used && (rc = hip_check(hipEventSynchronize(w->staged), "event synchronize"))) return rc;
-    BatchItem* hitems = (BatchItem*)w->hmeta;
-    BatchClass* hcls = (BatchClass*)(w->hmeta + items_b);
-    int* hnew = (int*)(w->hmeta + items_b + cls_b);
+    if ((rc = grow_pinned(w, meta_b))) return rc;
+
+    GroupItem* items = (GroupItem*)w->hmeta;
     int64_t pad_off = 0;
-    for (int t = 0; t < count; ++t) {
-        const ItemShape& sh = shapes[t];
-        BatchItem& it = hitems[t];
+    for (int j = 0; j < ni; ++j) {
+        const int t = list[(size_t)j];
+        GroupItem& it = items[j];
         it.src = dA + offs[t];
         it.src_n = ns[t];
         it.src_lda = std::max(ns[t], 1);
+        it.n = gp.n_eff[(size_t)j];
         it.A = it.src;
-        it.n = sh.n;
         it.lda = it.src_lda;
-        if (sh.kind == kItemComputed && sh.padded) {
-            it.A = w->pad + pad_off;
-            it.lda = sh.n;
-            pad_off += (int64_t)sh.n * sh.n;
-        }
-        it.out = d_out + t;
-        it.out_dd = nullptr;
-        it.slot0 = plan.slot0[t];
-        it.loops = sh.loops ? 1 : 0;
-        it.nslots = plan.item_slots[t];
-        it.kind = sh.kind;
+        it.cval = gp.cval[(size_t)j];
         it.pad_ = 0;
-        hnew[t] = t;
+        if (it.cval == kGroupComputed && it.n != ns[t]) {   // odd-n loop hafnian: dense padded copy
+            it.A = w->pad + pad_off;
+            it.lda = it.n;
+            pad_off += (int64_t)it.n * it.n;
+        }
+        it.out = d_out ? d_out + t : nullptr;
+        it.out_dd = d_out_dd ? d_out_dd + 4 * (int64_t)t : nullptr;
+        it.slot_base = gp.slot_base[(size_t)j];
+        it.nslots = gp.nslots[(size_t)j];
     }
-    for (size_t c = 0; c < plan.cls[0].size(); ++c) hcls[c] = plan.cls[0][c];
-    for (size_t c = 0; c < plan.cls[1].size(); ++c) hcls[plan.cls[0].size() + c] = plan.cls[1][c];
-    if ((rc = hip_check(hipMemcpyAsync(w->dmeta, w->hmeta, meta_b, hipMemcpyHostToDevice, st), "plan upload")))
+    if (!gp.chunks.empty())
+        std::memcpy(w->hmeta + items_b, gp.chunks.data(), sizeof(GroupChunk) * gp.chunks.size());
+    if ((rc = hip_check(hipMemcpyAsync(w->dmeta, w->hmeta, meta_b, hipMemcpyHostToDevice, st), "batch table upload")))
         return rc;
     if ((rc = hip_check(hipEventRecord(w->staged, st), "event record"))) return rc;
     w->staged_used = true;
-
-    const BatchItem* ditems = (const BatchItem*)w->dmeta;
-    const BatchClass* dcls = (const BatchClass*)(w->dmeta + items_b);
-    const int* dnew = (const int*)(w->dmeta + items_b + cls_b);
+    const GroupItem* ditems = (const GroupItem*)w->dmeta;
+    const GroupChunk* dch = (const GroupChunk*)(w->dmeta + items_b);
     int* exps = w->dstate;
-    int* done = w->dstate + count;
-    int* cursor = w->dstate + 2 * count;
-    if ((rc = hip_check(launch_batch_prologue(st, ditems, dnew, count, exps, done, cursor), "batch prologue launch")))
-        return rc;
-    // the large subsets first (fewest, longest chunks), then the rest
-    for (int L = 0; L < 2; ++L) {
-        if (plan.nchunks[L] == 0) continue;
-        const BatchClass* c0 = dcls + (L == 0 ? 0 : plan.cls[0].size());
-        const int pidx = prof_begin(st, 2, plan.flops[L], 0);
-        rc = hip_check(launch_batched(plan.variant[L], grid[L], st, ditems, c0, (int)plan.cls[L].size(),
-                                      (int)plan.nchunks[L], cursor + L, done, exps, w->part, w->coef),
-                       "batched kernel launch");
-        prof_end(pidx, st);
-        if (rc) return rc;
+
+    if ((rc = hip_check(launch_group_prologue(st, ditems, ni, exps), "batch prologue launch"))) return rc;
+    for (const StageLaunch& L : gp.launches) {
+        hipError_t e;
+        if (L.what == 0) {
+            int64_t subsets = 0;
+            for (int c = 0; c < L.nch; ++c) subsets += gp.chunks[L.first + (size_t)c].count;
+            const int pidx = prof_begin(st, 2, L.flops, subsets);
+            e = launch_coef_reg_group(L.layout, L.loops, L.blocks, st, ditems, dch + L.first, L.nch, exps, w->coef);
+            prof_end(pidx, st);
+        } else {
+            e = launch_series_group(L.loops, L.blocks, st, dch + L.first, L.nch, w->coef, w->part);
+        }
+        if ((rc = hip_check(e, "batch kernel launch"))) return rc;
     }
-    // matrices beyond the batched kernel's largest layout: single-matrix path, same stream
-    for (int t = 0; t < count; ++t)
-        if (shapes[t].kind == kItemExternal &&
-            (rc = run_dev(dA + offs[t], ns[t], std::max(ns[t], 1), kinds[t], nullptr, d_out + t, st)))
-            return rc;
-    return HAF_OK;
+    return hip_check(launch_reduce_group(st, ditems, ni, w->part, exps), "batch reduce launch");
 }
 
-// ------------------------------------------------------------------ stream-pool batches
+// ------------------------------------------------------------------ stream pool
 // Streams (default priority, non-blocking) owned by the library per device,
 // with an event per stream for joining back into the caller's stream.
 struct StreamPool {
@@ -377,261 +377,81 @@ static int stream_pool(int dev, int want, StreamPool** out) {
 }
 
 // Model flops of one whole matrix (every subset through the coefficient stage).
-static double item_cost(int n, int kind) {
-    const ItemShape sh = classify_item(n, kind);
+double item_cost(int n, int kind) {
     double f = 2.0e5;                                   // launch and series overhead, in flop units
-    if (sh.kind == kItemComputed || sh.kind == kItemExternal)
-        for (int m = 1; m <= sh.N; ++m) f += (double)binom(sh.N, m) * coef_model_flops(2 * m, sh.N, sh.loops);
+    if (constant_of(n, kind) != kGroupComputed) return f;
+    const int N = eff_n(n, kind) / 2;
+    for (int m = 1; m <= N; ++m) f += (double)binom(N, m) * coef_model_flops(2 * m, N, kind == HAF_KIND_LHAF);
     return f;
 }
 
-// ------------------------------------------------------------------ same-size groups
-// Matrices with 2 <= n <= 32 (after the odd-n loop-hafnian padding) go through
-// shared launches per (n, kind): one prologue, one coefficient launch per layout
-// run and sub-batch, one series launch per sub-batch, one reduction per group.
-// Each matrix keeps the single-matrix path's coefficients, slots and reduction.
-constexpr size_t kGroupCoefBudget = size_t(256) << 20;   // coefficient bytes per sub-batch
-
-static bool groupable(int n, int kind) {
-    if (n == 0 || (n % 2 == 1 && kind == HAF_KIND_HAF)) return false;   // constant results
-    const int eff = n % 2 == 1 ? n + 1 : n;
-    return eff >= 2 && eff <= 32;
-}
-
-static int run_grouped(const double2* dA, const int64_t* offs, const int32_t* ns, const uint8_t* kinds,
-                       const std::vector<int>& list, double2* d_out, hipStream_t st) {
-    if (list.empty()) return HAF_OK;
-    BatchWS* w = nullptr;
-    int rc = batch_ws(st, &w);
-    if (rc) return rc;
-    // matrices ordered by (n, kind), stable in the caller's order
-    std::vector<int> order(list);
-    auto eff = [&](int t) { return ns[t] % 2 == 1 ? ns[t] + 1 : ns[t]; };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return eff(a) != eff(b) ? eff(a) < eff(b) : kinds[a] < kinds[b];
-    });
-    const int ni = (int)order.size();
-    std::vector<GroupItem> items((size_t)ni);
-    std::vector<int64_t> padoff((size_t)ni, -1);             // offset of a padded copy in w->pad
-    struct Launch { int kind; int s_max; int N; bool loops; int blocks; size_t first; int nch; };
-    std::vector<GroupChunk> chunks;
-    std::vector<Launch> launches;                            // kind 0 coef, 1 series, 2 reduce (first = item)
-    int64_t slot = 0, pad_elems = 0, coef_max = 0;
-    for (int g0 = 0; g0 < ni;) {
-        const int n = eff(order[g0]), kind = kinds[order[g0]];
-        int g1 = g0;
-        while (g1 < ni && eff(order[g1]) == n && kinds[order[g1]] == kind) ++g1;
-        const Plan plan = make_plan(n, kind, kChunk);
-        const bool loops = kind == HAF_KIND_LHAF;
-        for (int j = g0; j < g1; ++j) {
-            const int t = order[j];
-            GroupItem& it = items[(size_t)j];
-            it.src = dA + offs[t];
-            it.src_n = ns[t];
-            it.src_lda = std::max(ns[t], 1);
-            it.n = n;
-            it.A = it.src;
-            it.lda = it.src_lda;
-            if (n != ns[t]) {                            // odd-n loop hafnian: dense padded copy
-                padoff[(size_t)j] = pad_elems;
-                it.lda = n;
-                pad_elems += (int64_t)n * n;
-            }
-            it.out = d_out + t;
-            it.slot_base = slot;
-            it.nslots = plan.nslots;
-            slot += plan.nslots;
-        }
-        // sub-batches bounded by the coefficient budget
-        const int64_t per_item = (int64_t)((1u << plan.N) - 1) * plan.ncoef;
-        const int per_batch = (int)std::max<int64_t>(1, (int64_t)(kGroupCoefBudget / sizeof(double2)) / per_item);
-        for (int b0 = g0; b0 < g1; b0 += per_batch) {
-            const int b1 = std::min(g1, b0 + per_batch);
-            coef_max = std::max<int64_t>(coef_max, (int64_t)(b1 - b0) * per_item);
-            // coefficient offsets: item-major, classes in plan order
-            std::vector<int64_t> coff((size_t)(b1 - b0) * plan.chunks.size());
-            int64_t off = 0;
-            for (int j = b0; j < b1; ++j)
-                for (size_t c = 0; c < plan.chunks.size(); ++c) {
-                    coff[(size_t)(j - b0) * plan.chunks.size() + c] = off;
-                    off += (int64_t)plan.chunks[c].count * plan.ncoef;
-                }
-            // one coefficient launch per run of classes sharing a layout
-            for (size_t c0 = 0; c0 < plan.chunks.size();) {
-                const int lay = reg_layout_index(2 * plan.chunks[c0].m);
-                size_t c1 = c0;
-                while (c1 < plan.chunks.size() && reg_layout_index(2 * plan.chunks[c1].m) == lay) ++c1;
-                const int s_max = 2 * plan.chunks[c1 - 1].m;
-                Launch L{ 0, s_max, plan.N, loops, 0, chunks.size(), 0 };
-                for (int j = b0; j < b1; ++j)
-                    for (size_t c = c0; c < c1; ++c) {
-                        GroupChunk ch{};
-                        ch.item = j;
-                        ch.m = plan.chunks[c].m;
-                        ch.count = plan.chunks[c].count;
-                        ch.gstart = L.blocks;
-                        ch.coff = coff[(size_t)(j - b0) * plan.chunks.size() + c];
-                        L.blocks += group_coef_blocks(s_max, ch.count);
-                        chunks.push_back(ch);
-                        ++L.nch;
-                    }
-                launches.push_back(L);
-                c0 = c1;
-            }
-            Launch S{ 1, 0, plan.N, loops, 0, chunks.size(), 0 };
-            for (int j = b0; j < b1; ++j)
-                for (size_t c = 0; c < plan.chunks.size(); ++c) {
-                    GroupChunk ch{};
-                    ch.item = j;
-                    ch.m = plan.chunks[c].m;
-                    ch.count = plan.chunks[c].count;
-                    ch.gstart = S.blocks;
-                    ch.coff = coff[(size_t)(j - b0) * plan.chunks.size() + c];
-                    ch.slot = items[(size_t)j].slot_base + plan.chunks[c].slot0;
-                    ch.sign = ((plan.N - ch.m) & 1) ? -1.0 : 1.0;
-                    S.blocks += group_series_blocks(ch.count);
-                    chunks.push_back(ch);
-                    ++S.nch;
-                }
-            launches.push_back(S);
-        }
-        launches.push_back(Launch{ 2, 0, plan.N, loops, 0, (size_t)g0, g1 - g0 });
-        g0 = g1;
-    }
-
-    // device buffers
-    if (pad_elems && (rc = grow((void**)&w->pad, &w->pad_cap, sizeof(double2) * (size_t)pad_elems, st))) return rc;
-    for (int j = 0; j < ni; ++j)
-        if (padoff[(size_t)j] >= 0) items[(size_t)j].A = w->pad + padoff[(size_t)j];
-    if ((rc = grow((void**)&w->coef, &w->coef_cap, sizeof(double2) * (size_t)std::max<int64_t>(coef_max, 1), st)))
-        return rc;
-    if ((rc = grow((void**)&w->part, &w->part_cap, sizeof(double) * 4 * (size_t)std::max<int64_t>(slot, 1), st)))
-        return rc;
-    if ((rc = grow((void**)&w->dstate, &w->dstate_cap, sizeof(int) * (size_t)ni, st))) return rc;
-    const size_t items_b = align256(sizeof(GroupItem) * items.size());
-    const size_t meta_b = items_b + align256(sizeof(GroupChunk) * std::max<size_t>(chunks.size(), 1));
-    if ((rc = grow((void**)&w->dmeta, &w->dmeta_cap, meta_b, st))) return rc;
-    if (w->staged_used && (rc = hip_check(hipEventSynchronize(w->staged), "event synchronize"))) return rc;
-    if ((rc = grow_pinned(w, meta_b))) return rc;
-    std::memcpy(w->hmeta, items.data(), sizeof(GroupItem) * items.size());
-    if (!chunks.empty()) std::memcpy(w->hmeta + items_b, chunks.data(), sizeof(GroupChunk) * chunks.size());
-    if ((rc = hip_check(hipMemcpyAsync(w->dmeta, w->hmeta, meta_b, hipMemcpyHostToDevice, st), "group table upload")))
-        return rc;
-    if ((rc = hip_check(hipEventRecord(w->staged, st), "event record"))) return rc;
-    w->staged_used = true;
-    const GroupItem* ditems = (const GroupItem*)w->dmeta;
-    const GroupChunk* dch = (const GroupChunk*)(w->dmeta + items_b);
-    int* exps = w->dstate;
-
-    if ((rc = hip_check(launch_group_prologue(st, ditems, ni, exps), "group prologue launch"))) return rc;
-    for (const Launch& L : launches) {
-        hipError_t e = hipSuccess;
-        if (L.kind == 0) {
-            const int pidx = prof_begin(st, 2, 0.0, 0);
-            e = launch_coef_reg_group(L.s_max, L.loops, L.blocks, st, ditems, dch + L.first, L.nch, L.N, exps, w->coef);
-            prof_end(pidx, st);
-        } else if (L.kind == 1) {
-            e = launch_series_group(L.N, L.loops, L.blocks, st, dch + L.first, L.nch, w->coef, w->part);
-        } else {
-            e = launch_reduce_group(st, ditems + L.first, L.nch, w->part, exps + L.first, L.N);
-        }
-        if ((rc = hip_check(e, "group kernel launch"))) return rc;
-    }
-    return HAF_OK;
-}
-
-int run_batched_streams(const double2* dA, const int64_t* offs, const int32_t* ns, const uint8_t* kinds, int count,
-                        double2* d_out, hipStream_t st, const haf_batched_config& cfg) {
-    int rc = check_batch_args(dA, offs, ns, kinds, count, d_out);
+int run_batched(const double2* dA, const int64_t* offs, const int32_t* ns, const uint8_t* kinds, int count,
+                double2* d_out, double* d_out_dd, hipStream_t st, const haf_batched_config& cfg) {
+    int rc = check_batch_args(dA, offs, ns, kinds, count, d_out ? (const void*)d_out : (const void*)d_out_dd);
     if (rc || count == 0) return rc;
     int dev = 0;
     if ((rc = ensure_device(&dev))) return rc;
-    const int nst = std::max(1, std::min(cfg.streams, 16));
-    StreamPool* pool = nullptr;
-    if ((rc = stream_pool(dev, nst, &pool))) return rc;
 
-    // largest first, each to the stream with the least work so far
-    std::vector<int> order((size_t)count);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<double> cost((size_t)count);
-    for (int t = 0; t < count; ++t) cost[t] = item_cost(ns[t], kinds[t]);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<int> grouped, rest;
+    for (int t = 0; t < count; ++t) (cfg.grouped && groupable(ns[t], kinds[t]) ? grouped : rest).push_back(t);
+    // the rest: largest model cost first, each to the stream with the least work so far
+    std::vector<double> cost((size_t)count, 0.0);
+    for (int t : rest) cost[(size_t)t] = item_cost(ns[t], kinds[t]);
+    std::stable_sort(rest.begin(), rest.end(), [&](int a, int b) { return cost[(size_t)a] > cost[(size_t)b]; });
+    const int nst = std::max(1, std::min(cfg.streams, kMaxPoolStreams));
     std::vector<std::vector<int>> lists((size_t)nst);
     std::vector<double> load((size_t)nst, 0.0);
-    // same-size groups go out in shared launches on pool stream 0
-    std::vector<int> grouped;
-    if (cfg.grouped) {
-        std::vector<int> rest;
-        for (int t : order) {
-            if (groupable(ns[t], kinds[t])) {
-                grouped.push_back(t);
-                load[0] += cost[t];
-            } else {
-                rest.push_back(t);
-            }
-        }
-        std::sort(grouped.begin(), grouped.end());
-        order.swap(rest);
-    }
-    for (int t : order) {
+    for (int t : rest) {
         const int p = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        lists[p].push_back(t);
-        load[p] += cost[t];
+        lists[(size_t)p].push_back(t);
+        load[(size_t)p] += cost[(size_t)t];
     }
-
-    // the pool streams start after the work already on st
-    if ((rc = hip_check(hipEventRecord(pool->start, st), "event record"))) return rc;
-    for (int p = 0; p < nst; ++p)
-        if ((rc = hip_check(hipStreamWaitEvent(pool->st[p], pool->start, 0), "stream wait"))) return rc;
-
+    StreamPool* pool = nullptr;
+    if (!rest.empty()) {
+        if ((rc = stream_pool(dev, nst, &pool))) return rc;
+        // the pool streams start after the work already on st
+        if ((rc = hip_check(hipEventRecord(pool->start, st), "event record"))) return rc;
+        for (int p = 0; p < nst; ++p)
+            if ((rc = hip_check(hipStreamWaitEvent(pool->st[(size_t)p], pool->start, 0), "stream wait"))) return rc;
+    }
     std::vector<int> rcs((size_t)nst, HAF_OK);
     std::vector<std::string> msgs((size_t)nst);
     auto worker = [&](int p) {
         if (hipSetDevice(dev) != hipSuccess) {
-            rcs[p] = HAF_E_DEVICE;
-            msgs[p] = "hipSetDevice failed";
+            rcs[(size_t)p] = HAF_E_DEVICE;
+            msgs[(size_t)p] = "hipSetDevice failed";
             return;
         }
-        if (p == 0 && !grouped.empty()) {
-            const int r = run_grouped(dA, offs, ns, kinds, grouped, d_out, pool->st[0]);
+        for (int t : lists[(size_t)p]) {
+            const int r = run_dev(dA + offs[t], ns[t], std::max(ns[t], 1), kinds[t],
+                                  d_out_dd ? d_out_dd + 4 * (int64_t)t : nullptr, d_out ? d_out + t : nullptr,
+                                  pool->st[(size_t)p]);
             if (r) {
-                rcs[p] = r;
-                msgs[p] = last_error();
-                return;
-            }
-        }
-        for (int t : lists[p]) {
-            const int r = run_dev(dA + offs[t], ns[t], std::max(ns[t], 1), kinds[t], nullptr, d_out + t,
-                                  pool->st[p]);
-            if (r) {
-                rcs[p] = r;
-                msgs[p] = last_error();
+                rcs[(size_t)p] = r;
+                msgs[(size_t)p] = last_error();
                 return;
             }
         }
     };
-    if (nst == 1) {
-        worker(0);
-    } else {
-        std::vector<std::thread> th;
+    std::vector<std::thread> th;
+    if (!rest.empty())
         for (int p = 0; p < nst; ++p)
-            if (!lists[p].empty() || (p == 0 && !grouped.empty())) th.emplace_back(worker, p);
-        for (auto& x : th) x.join();
+            if (!lists[(size_t)p].empty()) th.emplace_back(worker, p);
+    const int grc = run_grouped(dA, offs, ns, kinds, grouped, d_out, d_out_dd, st, cfg);
+    const std::string gmsg = grc ? last_error() : std::string();
+    for (auto& x : th) x.join();
+    if (!rest.empty()) {
+        // join back: st waits for every pool stream (also after an error, so that
+        // nothing enqueued so far is left unordered with the caller's stream)
+        for (int p = 0; p < nst; ++p) {
+            (void)hipEventRecord(pool->done[(size_t)p], pool->st[(size_t)p]);
+            (void)hipStreamWaitEvent(st, pool->done[(size_t)p], 0);
+        }
     }
-    // join back: st waits for every pool stream (also after an error, so that
-    // nothing enqueued so far is left unordered with the caller's stream)
-    for (int p = 0; p < nst; ++p) {
-        (void)hipEventRecord(pool->done[p], pool->st[p]);
-        (void)hipStreamWaitEvent(st, pool->done[p], 0);
-    }
+    if (grc) return set_error(grc, "%s", gmsg.c_str());
     for (int p = 0; p < nst; ++p)
-        if (rcs[p]) return set_error(rcs[p], "%s", msgs[p].c_str());
+        if (rcs[(size_t)p]) return set_error(rcs[(size_t)p], "%s", msgs[(size_t)p].c_str());
     return HAF_OK;
-}
-
-int run_batched(const double2* dA, const int64_t* offs, const int32_t* ns, const uint8_t* kinds, int count,
-                double2* d_out, hipStream_t st, const haf_batched_config& cfg) {
-    return run_batched_streams(dA, offs, ns, kinds, count, d_out, st, cfg);
 }
 
 }  // namespace hafgpu
@@ -644,7 +464,16 @@ extern "C" {
 int haf_batched_c128(const haf_cplx* dA_packed, const int64_t* h_offsets, const int32_t* h_n,
                      const uint8_t* h_kind, int count, haf_cplx* d_out, void* stream) {
     clear_error();
-    return run_batched((const double2*)dA_packed, h_offsets, h_n, h_kind, count, (double2*)d_out,
+    if (count > 0 && !d_out) return set_error(HAF_E_INVALID_ARG, "null output");
+    return run_batched((const double2*)dA_packed, h_offsets, h_n, h_kind, count, (double2*)d_out, nullptr,
+                       (hipStream_t)stream, batch_config());
+}
+
+int haf_batched_c128x2(const haf_cplx* dA_packed, const int64_t* h_offsets, const int32_t* h_n,
+                       const uint8_t* h_kind, int count, haf_cplx2* d_out, void* stream) {
+    clear_error();
+    if (count > 0 && !d_out) return set_error(HAF_E_INVALID_ARG, "null output");
+    return run_batched((const double2*)dA_packed, h_offsets, h_n, h_kind, count, nullptr, (double*)d_out,
                        (hipStream_t)stream, batch_config());
 }
 
@@ -658,15 +487,8 @@ int haf_batched_get_config(haf_batched_config* cfg) {
 int haf_batched_set_config(const haf_batched_config* cfg) {
     clear_error();
     if (!cfg) return set_error(HAF_E_INVALID_ARG, "null pointer");
-    if (cfg->layout < 0 || cfg->layout > 2) return set_error(HAF_E_INVALID_ARG, "layout %d not in 0..2", cfg->layout);
-    if (cfg->group_work < 1 || cfg->group_work > 4096)
-        return set_error(HAF_E_INVALID_ARG, "group_work %d not in 1..4096", cfg->group_work);
-    if (cfg->waves_per_cu < 0 || cfg->waves_per_cu > 64)
-        return set_error(HAF_E_INVALID_ARG, "waves_per_cu %d not in 0..64", cfg->waves_per_cu);
-    if (cfg->streams < 1 || cfg->streams > 16)
-        return set_error(HAF_E_INVALID_ARG, "streams %d not in 1..16", cfg->streams);
-    if (cfg->grouped != 0 && cfg->grouped != 1)
-        return set_error(HAF_E_INVALID_ARG, "grouped %d not 0 or 1", cfg->grouped);
+    const int rc = check_config(*cfg);
+    if (rc) return rc;
     set_batch_config(*cfg);
     return HAF_OK;
 }
@@ -681,28 +503,51 @@ int haf_batched_tune(const haf_cplx* dA_packed, const int64_t* h_offsets, const 
     hipEvent_t a = nullptr, b = nullptr;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
         return set_error(HAF_E_DEVICE, "hipEventCreate failed");
-    std::vector<haf_batched_config> cand;
     const haf_batched_config keep = batch_config();
-    for (int grp : { 1, 0 })
-        for (int nst : { 1, 2, 4, 8, 16 }) {
-            haf_batched_config c = keep;
-            c.grouped = grp;
-            c.streams = nst;
-            cand.push_back(c);
-        }
     haf_batched_config pick = keep;
     double pick_ms = 1e300;
-    for (const haf_batched_config& c : cand) {
-        rc = run_batched((const double2*)dA_packed, h_offsets, h_n, h_kind, count, (double2*)d_out, st, c);
-        if (!rc) rc = hip_check(hipEventRecord(a, st), "event record");
-        if (!rc)
-            rc = run_batched((const double2*)dA_packed, h_offsets, h_n, h_kind, count, (double2*)d_out, st, c);
-        if (!rc) rc = hip_check(hipEventRecord(b, st), "event record");
-        if (!rc) rc = hip_check(hipEventSynchronize(b), "event synchronize");
+    // one configuration: a warm run (workspaces), then a timed run
+    auto trial = [&](const haf_batched_config& c) -> int {
+        int r = run_batched((const double2*)dA_packed, h_offsets, h_n, h_kind, count, (double2*)d_out, nullptr, st,
+                            c);
+        if (!r) r = hip_check(hipEventRecord(a, st), "event record");
+        if (!r)
+            r = run_batched((const double2*)dA_packed, h_offsets, h_n, h_kind, count, (double2*)d_out, nullptr, st,
+                            c);
+        if (!r) r = hip_check(hipEventRecord(b, st), "event record");
+        if (!r) r = hip_check(hipEventSynchronize(b), "event synchronize");
         float ms = 0.f;
-        if (!rc) rc = hip_check(hipEventElapsedTime(&ms, a, b), "event time");
-        if (rc) break;
-        if (ms < pick_ms) { pick_ms = ms; pick = c; }
+        if (!r) r = hip_check(hipEventElapsedTime(&ms, a, b), "event time");
+        if (!r && ms < pick_ms) {
+            pick_ms = ms;
+            pick = c;
+        }
+        return r;
+    };
+    // coordinate search: subsets per lane group, then the layout table, then the
+    // streams of the large matrices; the single-matrix launches for reference
+    for (int span : { 1, 2, 4, 8, 16 }) {
+        haf_batched_config c = keep;
+        c.grouped = 1;
+        c.table = 0;
+        c.span = span;
+        if ((rc = trial(c))) break;
+    }
+    if (!rc) {
+        haf_batched_config c = pick;
+        c.table = 1 - pick.table;
+        rc = trial(c);
+    }
+    for (int nst = 1; !rc && nst <= kMaxPoolStreams; nst *= 2) {
+        haf_batched_config c = pick;
+        c.streams = nst;
+        if (c.streams != pick.streams) rc = trial(c);
+    }
+    if (!rc) {
+        haf_batched_config c = pick;
+        c.grouped = 0;
+        c.streams = kMaxPoolStreams;
+        rc = trial(c);
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
@@ -716,30 +561,36 @@ int haf_batched_tune(const haf_cplx* dA_packed, const int64_t* h_offsets, const 
     return HAF_OK;
 }
 
-int haf_batched_plan(const int32_t* h_n, const uint8_t* h_kind, int count, int32_t* classes, int max_classes,
-                     int* n_classes, int64_t* n_chunks, int* variant) {
+int haf_batched_plan(const int32_t* h_n, const uint8_t* h_kind, int count, int64_t* launches, int max_launches,
+                     int* n_launches, int64_t* chunks, int max_chunks, int* n_chunks) {
     clear_error();
-    if (count < 0 || (count > 0 && (!h_n || !h_kind)) || !n_classes || !n_chunks || !variant)
+    if (count < 0 || (count > 0 && (!h_n || !h_kind)) || !n_launches || !n_chunks)
         return set_error(HAF_E_INVALID_ARG, "bad argument");
     for (int t = 0; t < count; ++t)
-        if (h_n[t] < 0 || (h_kind[t] != HAF_KIND_HAF && h_kind[t] != HAF_KIND_LHAF))
+        if (h_n[t] < 0 || (h_kind[t] != HAF_KIND_HAF && h_kind[t] != HAF_KIND_LHAF) ||
+            eff_n(h_n[t], h_kind[t]) > HAF_MAX_N)
             return set_error(HAF_E_INVALID_ARG, "bad item %d", t);
-    BatchPlan plan;
-    int rc = plan_batch(h_n, h_kind, count, batch_config(), &plan);
+    const haf_batched_config cfg = batch_config();
+    std::vector<int> list;
+    for (int t = 0; t < count; ++t)
+        if (cfg.grouped && groupable(h_n[t], h_kind[t])) list.push_back(t);
+    GroupPlan gp;
+    const int rc = plan_groups(h_n, h_kind, list, cfg, &gp);
     if (rc) return rc;
-    *n_chunks = plan.nchunks[0] + plan.nchunks[1];
-    *n_classes = (int)(plan.cls[0].size() + plan.cls[1].size());
-    *variant = plan.variant[1];
-    int c = 0;
-    for (int L = 0; L < 2; ++L)
-        for (const BatchClass& k : plan.cls[L]) {
-            if (classes && c < max_classes) {
-                int32_t* o = classes + 8 * c;
-                o[0] = k.item; o[1] = k.m; o[2] = k.cap; o[3] = k.total;
-                o[4] = k.j0; o[5] = k.chunk_base; o[6] = k.slot_base; o[7] = plan.item_slots[k.item];
-            }
-            ++c;
-        }
+    *n_launches = (int)gp.launches.size();
+    *n_chunks = (int)gp.chunks.size();
+    for (size_t l = 0; l < gp.launches.size() && launches && (int)l < max_launches; ++l) {
+        const StageLaunch& L = gp.launches[l];
+        int64_t* o = launches + 8 * l;
+        o[0] = L.what; o[1] = L.layout; o[2] = L.loops; o[3] = L.blocks;
+        o[4] = (int64_t)L.first; o[5] = L.nch; o[6] = L.coef_elems; o[7] = reg_layout_sm(L.layout);
+    }
+    for (size_t c = 0; c < gp.chunks.size() && chunks && (int)c < max_chunks; ++c) {
+        const GroupChunk& ch = gp.chunks[c];
+        int64_t* o = chunks + 8 * c;
+        o[0] = gp.order[(size_t)ch.item]; o[1] = ch.m; o[2] = ch.count; o[3] = ch.gstart;
+        o[4] = ch.coff; o[5] = ch.slot; o[6] = ch.N; o[7] = (int64_t)ch.rank0;
+    }
     return HAF_OK;
 }
 

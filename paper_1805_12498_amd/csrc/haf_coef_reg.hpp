@@ -227,7 +227,7 @@ __device__ __forceinline__ void write_coefs_range(double2* __restrict__ coef, in
 // matrix, 1 = the whole wave on one matrix at a time with the rows split over the
 // W lane groups, 2 = one matrix per wave, degrees in two passes (below 32 with the
 // rows split over the two lane halves, then the rest).
-template <int P, int Q, int R, int C, int CP, bool LOOPS, bool ELIM = false>
+template <int P, int Q, int R, int C, int CP, bool LOOPS>
 __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const double2* __restrict__ A, int lda,
                                               int N, int m, uint64_t rank0, int count,
                                               const uint32_t* __restrict__ masks, double off_scale,
@@ -300,149 +300,6 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             __builtin_amdgcn_s_setprio(0);
         }
 
-        if constexpr (ELIM) {
-        // ---- reduction to upper Hessenberg form by elimination with row and column
-        // exchanges (the similarity L^-1 Pi H Pi L of each step): the characteristic
-        // polynomial is that of B for any similarity (App. B); this one needs half the
-        // work of the Householder form and no square root.
-        //   step j: pivot p = the row in (j, s) with the largest |Re| + |Im| in column j;
-        //   exchange rows and columns j+1 and p; l_r = H[r][j] / H[j+1][j] for r > j+1;
-        //   rows r > j+1 -= l_r row j+1; then column j+1 += sum_{c > j+1} l_c column c.
-        // Entries below the subdiagonal are left stale: nothing reads them.
-        double2* rowp = vv;                   // old row p (the pivot row after the exchange)
-        double2* rowj = wb;                   // old row j+1
-        double2* colj = yb;                   // old column j+1
-        double2* colp = wpart;                // old column p
-        if (b == 0) {                          // column 0 -> colb
-#pragma unroll
-            for (int t = 0; t < R; ++t)
-                if (a + P * t < SM) colb[a + P * t] = h[t][0];
-        }
-        const uint64_t gmask = (L == 64) ? ~0ull : (((1ull << L) - 1ull) << (g * L));
-        for (int j = 0; j + 2 < s; ++j) {
-            __syncthreads();                  // column j is in colb
-            const double2 x = (lam > j && lam < s) ? colb[lam] : cz();
-            const double key = (lam > j && lam < s) ? fabs(x.x) + fabs(x.y) : -1.0;
-            const double mx = group_max<L>(key);
-            const bool skip = !(mx > 0.0);
-            const uint64_t hits = __ballot(key == mx) & gmask;
-            const int p = skip ? j + 1 : (int)__builtin_ctzll(hits) - g * L;
-            const double2 piv = colb[p];
-            // 1 / piv, scaled so that |piv|^2 cannot under- or overflow
-            double2 inv = cz();
-            if (!skip) {
-                const double sc = 1.0 / (fabs(piv.x) + fabs(piv.y));
-                const double2 pn = cscale(piv, sc);
-                const double d = sc / fma(pn.x, pn.x, pn.y * pn.y);
-                inv = make_double2(pn.x * d, -pn.y * d);
-            }
-            const bool swap = p != j + 1;
-            // publish the old rows p and j+1 and the old columns j+1 and p
-#pragma unroll
-            for (int t = 0; t < R; ++t) {
-                const int r = a + P * t;
-                if (r == p || (swap && r == j + 1)) {
-                    double2* dst = r == p ? rowp : rowj;
-#pragma unroll
-                    for (int u = 0; u < C; ++u)
-                        if (b + Q * u < SM) dst[b + Q * u] = h[t][u];
-                }
-            }
-            if (swap) {
-#pragma unroll
-                for (int u = 0; u < C; ++u) {
-                    const int c = b + Q * u;
-                    if (c == j + 1 || c == p) {
-                        double2* dst = c == j + 1 ? colj : colp;
-#pragma unroll
-                        for (int t = 0; t < R; ++t)
-                            if (a + P * t < SM) dst[a + P * t] = h[t][u];
-                    }
-                }
-            }
-            if (lam == 0) {
-                if (skip) beta[j + 1] = colb[j + 1];
-                else beta[j + 1] = piv;
-            }
-            __syncthreads();
-            // exchange: new[r][c] = old[pi(r)][pi(c)], pi swapping j+1 and p
-#define HAF_PI(i) ((i) == j + 1 ? p : ((i) == p ? j + 1 : (i)))
-            if (swap) {
-#pragma unroll
-                for (int t = 0; t < R; ++t) {
-                    const int r = a + P * t;
-                    if (r == j + 1 || r == p) {
-                        const double2* src = r == j + 1 ? rowp : rowj;
-#pragma unroll
-                        for (int u = 0; u < C; ++u)
-                            if (b + Q * u < SM) h[t][u] = src[HAF_PI(b + Q * u)];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < C; ++u) {
-                    const int c = b + Q * u;
-                    if (c == j + 1 || c == p) {
-                        const double2* src = c == j + 1 ? colp : colj;
-#pragma unroll
-                        for (int t = 0; t < R; ++t) {
-                            const int r = a + P * t;
-                            if (r < SM && r != j + 1 && r != p) h[t][u] = src[r];
-                        }
-                    }
-                }
-            }
-            // multipliers l_r = H[r][j] / H[j+1][j] after the exchange (zero at and above j+1)
-            const int ulo = (j + 1) / Q;      // column slots left of ulo hold only columns <= j
-            const int tlo = (j + 2) / P;      // row slots above tlo hold only rows <= j+1
-            double2 lr[R];
-#pragma unroll
-            for (int t = 0; t < R; ++t) {
-                const int r = a + P * t;
-                lr[t] = (r > j + 1 && r < s) ? cmul(colb[HAF_PI(r)], inv) : cz();
-            }
-            // one pass per column slot: rows below j+1 minus l_r times the pivot row (old
-            // row p, columns exchanged), then that column's share of sum_{c > j+1} l_c column c
-            double2 yp[R];
-#pragma unroll
-            for (int t = 0; t < R; ++t) yp[t] = cz();
-#pragma unroll
-            for (int u = 0; u < C; ++u)
-                if (u >= ulo) {
-                    const int c = b + Q * u;
-                    const double2 pr = c < SM ? rowp[HAF_PI(c)] : cz();
-                    const double2 lcu = (c > j + 1 && c < s) ? cmul(colb[HAF_PI(c)], inv) : cz();
-#pragma unroll
-                    for (int t = 0; t < R; ++t) {
-                        if (t >= tlo) cfms(h[t][u], lr[t], pr);
-                        cfma(yp[t], h[t][u], lcu);
-                    }
-                }
-#undef HAF_PI
-#pragma unroll
-            for (int t = 0; t < R; ++t) ypart[a + P * t + S::YB * b] = yp[t];
-            __syncthreads();
-            const int un = (j + 1) / Q, bn = (j + 1) % Q;
-            if (b == bn) {
-#pragma unroll
-                for (int u = 0; u < C; ++u)
-                    if (u == un) {
-#pragma unroll
-                        for (int t = 0; t < R; ++t) {
-                            double2 y = cz();
-#pragma unroll
-                            for (int bb = 0; bb < Q; ++bb) {
-                                const double2 pp = ypart[a + P * t + S::YB * bb];
-                                y.x += pp.x;
-                                y.y += pp.y;
-                            }
-                            h[t][u] = cadd(h[t][u], y);
-                            if (j + 3 < s && a + P * t < SM) colb[a + P * t] = h[t][u];
-                        }
-                    }
-            }
-        }
-
-        } else {
         // ---- Householder reduction to upper Hessenberg form
         if (b == 0) {                          // column 0 -> colb, its norm below row 1 -> nrmp
             double part = 0.0;
@@ -553,8 +410,6 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                     }
             }
         }
-
-        }
         __builtin_amdgcn_s_setprio(2);        // table, scaling walk: LDS latency chains
         // ---- the last subdiagonal entry (no reflector acts on it)
 #pragma unroll
@@ -650,15 +505,15 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
 
 
 // Layouts and the subset sizes each one serves: (P, Q, R, C, CP) for s in (lo, hi].
-// The "narrow" table packs two or four matrices per wave where the tile fits, in
-// steps of 4 rows from 8 up to 32 so that little of a tile is padding;
-// the "wide" table gives every matrix above s = 16 a full wave (smaller tiles,
-// fewer registers, more resident waves).
-#define HAF_REG_NARROW(X) X(4, 4, 2, 2, 0, 0, 8) X(4, 4, 3, 3, 0, 8, 12) X(4, 4, 4, 4, 0, 12, 16)       \
+// The table packs two or four matrices per wave where the tile fits, in steps of
+// 4 rows from 8 up to 32 so that little of a tile is padding.  A layout can serve
+// any s in (SM - 8, SM] (the polynomial stage is instantiated for those sizes),
+// and two layouts with the same P, Q and CP give bitwise the same results for a
+// subset (padded rows and columns only add exact zeros; every sum runs over the
+// same P or Q partials in the same order).
+#define HAF_REG_TABLE(X) X(4, 4, 2, 2, 0, 0, 8) X(4, 4, 3, 3, 0, 8, 12) X(4, 4, 4, 4, 0, 12, 16)       \
                           X(8, 4, 3, 5, 0, 16, 20) \
                           X(8, 4, 3, 6, 0, 20, 24) X(8, 4, 4, 7, 1, 24, 28) X(8, 4, 4, 8, 1, 28, 32)      \
                           X(8, 8, 5, 5, 2, 32, 40) X(8, 8, 6, 6, 2, 40, 48)
-#define HAF_REG_WIDE(X) X(8, 8, 3, 3, 2, 16, 24) X(8, 8, 4, 4, 2, 24, 32)
-#define HAF_REG_SHAPES(X) HAF_REG_NARROW(X) HAF_REG_WIDE(X)
 
 }  // namespace hafgpu

@@ -5,8 +5,8 @@
 
 namespace hafgpu {
 
-template <int P, int Q, int R, int C, int CP, bool LOOPS, bool ELIM>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((ELIM || R * C >= 36) ? 2 : 1))) void k_coef_reg(const double2* __restrict__ A, int lda, int N, int m,
+template <int P, int Q, int R, int C, int CP, bool LOOPS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 ? 2 : 1))) void k_coef_reg(const double2* __restrict__ A, int lda, int N, int m,
                                                  uint64_t rank0, int count, const uint32_t* __restrict__ masks,
                                                  const int* __restrict__ d_exp, double2* __restrict__ coef,
                                                  int64_t cstride) {
@@ -15,19 +15,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((ELIM || R *
     const int e = d_exp ? *d_exp : 0;
     const int groups = gridDim.x * S::W;
     const int span = (count + groups - 1) / groups;
-    coef_reg_span<P, Q, R, C, CP, LOOPS, ELIM>(lds, A, lda, N, m, rank0, count, masks, ldexp(1.0, -2 * e),
+    coef_reg_span<P, Q, R, C, CP, LOOPS>(lds, A, lda, N, m, rank0, count, masks, ldexp(1.0, -2 * e),
                                                ldexp(1.0, -e), coef, cstride, blockIdx.x * S::W, span, threadIdx.x);
 }
 
-#define HAF_INST_REG_E(P, Q, R, C, CP, LO, HI, E)                                                             \
-    template __global__ void k_coef_reg<P, Q, R, C, CP, false, E>(const double2*, int, int, int, uint64_t, int,   \
-                                                                  const uint32_t*, const int*, double2*, int64_t); \
-    template __global__ void k_coef_reg<P, Q, R, C, CP, true, E>(const double2*, int, int, int, uint64_t, int,    \
-                                                                 const uint32_t*, const int*, double2*, int64_t);
-#define HAF_INST_REG_H(P, Q, R, C, CP, LO, HI) HAF_INST_REG_E(P, Q, R, C, CP, LO, HI, false)
-#define HAF_INST_REG_EL(P, Q, R, C, CP, LO, HI) HAF_INST_REG_E(P, Q, R, C, CP, LO, HI, true)
-HAF_REG_SHAPES(HAF_INST_REG_H)
-HAF_REG_NARROW(HAF_INST_REG_EL)
+#define HAF_INST_REG(P, Q, R, C, CP, LO, HI)                                                                \
+    template __global__ void k_coef_reg<P, Q, R, C, CP, false>(const double2*, int, int, int, uint64_t, int,     \
+                                                               const uint32_t*, const int*, double2*, int64_t); \
+    template __global__ void k_coef_reg<P, Q, R, C, CP, true>(const double2*, int, int, int, uint64_t, int,      \
+                                                              const uint32_t*, const int*, double2*, int64_t);
+HAF_REG_TABLE(HAF_INST_REG)
 
 int reg_max_s() { return 48; }
 
@@ -45,7 +42,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 
     const int groups = (mc.gstart[c + 1] - mc.gstart[c]) * S::W;
     const int count = mc.count[c];
     const int span = (count + groups - 1) / groups;
-    coef_reg_span<P, Q, R, C, CP, LOOPS, false>(lds, A, lda, N, mc.m[c], mc.rank0[c], count, nullptr,
+    coef_reg_span<P, Q, R, C, CP, LOOPS>(lds, A, lda, N, mc.m[c], mc.rank0[c], count, nullptr,
                                                 ldexp(1.0, -2 * e), ldexp(1.0, -e), coef + mc.coff[c], count,
                                                 ((int)blockIdx.x - mc.gstart[c]) * S::W, span, threadIdx.x);
 }
@@ -55,13 +52,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 
                                                                      double2*, MultiChunks);                 \
     template __global__ void k_coef_reg_multi<P, Q, R, C, CP, true>(const double2*, int, int, const int*,    \
                                                                     double2*, MultiChunks);
-HAF_REG_NARROW(HAF_INST_REG_MULTI)
+HAF_REG_TABLE(HAF_INST_REG_MULTI)
 
-// Same-size matrices of a batch: the workgroup finds its chunk by a binary
-// search over the launch's chunk table (uniform), then runs the per-subset body.
+// Matrices of a batch: the workgroup finds its chunk by a binary search over
+// the launch's chunk table (uniform), then runs the per-subset body for the
+// chunk's matrix (its own N, exponent and subset ranks).
 template <int P, int Q, int R, int C, int CP, bool LOOPS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 ? 2 : 1))) void k_coef_reg_group(
-    const GroupItem* __restrict__ items, const GroupChunk* __restrict__ chunks, int nchunks, int N,
+    const GroupItem* __restrict__ items, const GroupChunk* __restrict__ chunks, int nchunks,
     const int* __restrict__ exps, double2* __restrict__ coef) {
     using S = RegShape<P, Q, R, C>;
     __shared__ double2 lds[S::W * S::PER];
@@ -78,38 +76,62 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 
     const int span = (ch.count + groups - 1) / groups;
     const GroupItem it = items[ch.item];
     const int e = exps[ch.item];
-    coef_reg_span<P, Q, R, C, CP, LOOPS, false>(lds, it.A, it.lda, N, ch.m, 0, ch.count, nullptr, ldexp(1.0, -2 * e),
-                                                ldexp(1.0, -e), coef + ch.coff, ch.count, (blk - ch.gstart) * S::W,
-                                                span, threadIdx.x);
+    coef_reg_span<P, Q, R, C, CP, LOOPS>(lds, it.A, it.lda, ch.N, ch.m, ch.rank0, ch.count, nullptr,
+                                         ldexp(1.0, -2 * e), ldexp(1.0, -e), coef + ch.coff, ch.count,
+                                         (blk - ch.gstart) * S::W, span, threadIdx.x);
 }
 
 #define HAF_INST_REG_GROUP(P, Q, R, C, CP, LO, HI)                                                          \
     template __global__ void k_coef_reg_group<P, Q, R, C, CP, false>(const GroupItem*, const GroupChunk*,   \
-                                                                     int, int, const int*, double2*);       \
+                                                                     int, const int*, double2*);            \
     template __global__ void k_coef_reg_group<P, Q, R, C, CP, true>(const GroupItem*, const GroupChunk*,    \
-                                                                    int, int, const int*, double2*);
-HAF_REG_NARROW(HAF_INST_REG_GROUP)
+                                                                    int, const int*, double2*);
+HAF_REG_TABLE(HAF_INST_REG_GROUP)
 
-int group_coef_blocks(int s_max, int count) {
-#define HAF_GB(P, Q, R, C, CP, LO, HI) \
-    if (s_max > LO && s_max <= HI) return (count + RegShape<P, Q, R, C>::W - 1) / RegShape<P, Q, R, C>::W;
-    HAF_REG_NARROW(HAF_GB)
-#undef HAF_GB
+int reg_layout_count() {
+    int i = 0;
+#define HAF_CNT(P, Q, R, C, CP, LO, HI) ++i;
+    HAF_REG_TABLE(HAF_CNT)
+#undef HAF_CNT
+    return i;
+}
+
+int reg_layout_sm(int layout) {
+    int i = 0;
+#define HAF_SM_OF(P, Q, R, C, CP, LO, HI) \
+    if (i++ == layout) return RegShape<P, Q, R, C>::SM;
+    HAF_REG_TABLE(HAF_SM_OF)
+#undef HAF_SM_OF
     return 0;
 }
 
-hipError_t launch_coef_reg_group(int s_max, bool loops, int blocks, hipStream_t st, const GroupItem* items,
-                                 const GroupChunk* chunks, int nchunks, int N, const int* exps, double2* coef) {
+int reg_layout_groups(int layout) {
+    int i = 0;
+#define HAF_W_OF(P, Q, R, C, CP, LO, HI) \
+    if (i++ == layout) return RegShape<P, Q, R, C>::W;
+    HAF_REG_TABLE(HAF_W_OF)
+#undef HAF_W_OF
+    return 0;
+}
+
+int group_coef_blocks(int layout, int count, int span) {
+    const int w = reg_layout_groups(layout) * (span > 0 ? span : 1);
+    return w > 0 ? (count + w - 1) / w : 0;
+}
+
+hipError_t launch_coef_reg_group(int layout, bool loops, int blocks, hipStream_t st, const GroupItem* items,
+                                 const GroupChunk* chunks, int nchunks, const int* exps, double2* coef) {
     if (nchunks < 1 || blocks < 1) return hipErrorInvalidValue;
+    int i = 0;
 #define HAF_TRY_GROUP(P, Q, R, C, CP, LO, HI)                                                                 \
-    if (s_max > LO && s_max <= HI) {                                                                          \
+    if (i++ == layout) {                                                                                      \
         if (loops) hipLaunchKernelGGL((k_coef_reg_group<P, Q, R, C, CP, true>), dim3(blocks), dim3(64), 0, st, \
-                                      items, chunks, nchunks, N, exps, coef);                                 \
+                                      items, chunks, nchunks, exps, coef);                                    \
         else hipLaunchKernelGGL((k_coef_reg_group<P, Q, R, C, CP, false>), dim3(blocks), dim3(64), 0, st,     \
-                                items, chunks, nchunks, N, exps, coef);                                       \
+                                items, chunks, nchunks, exps, coef);                                          \
         return hipGetLastError();                                                                             \
     }
-    HAF_REG_NARROW(HAF_TRY_GROUP)
+    HAF_REG_TABLE(HAF_TRY_GROUP)
 #undef HAF_TRY_GROUP
     return hipErrorInvalidValue;
 }
@@ -119,7 +141,7 @@ int reg_layout_index(int s) {
 #define HAF_IDX(P, Q, R, C, CP, LO, HI) \
     if (s > LO && s <= HI) return i;    \
     ++i;
-    HAF_REG_NARROW(HAF_IDX)
+    HAF_REG_TABLE(HAF_IDX)
 #undef HAF_IDX
     return -1;
 }
@@ -145,33 +167,27 @@ hipError_t launch_coef_reg_multi(int s_max, bool loops, int grid_waves, hipStrea
                                 N, d_exp, coef, mc);                                                          \
         return hipGetLastError();                                                                             \
     }
-    HAF_REG_NARROW(HAF_TRY_MULTI)
+    HAF_REG_TABLE(HAF_TRY_MULTI)
 #undef HAF_TRY_MULTI
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_coef_reg(int s, bool loops, int grid_waves, hipStream_t st, const double2* A, int lda, int N,
                            int m, uint64_t rank0, int count, const uint32_t* masks, const int* d_exp,
-                           double2* coef, int64_t cstride, bool wide, bool elim) {
+                           double2* coef, int64_t cstride) {
     if (count <= 0) return hipSuccess;
-#define HAF_TRY_REG(P, Q, R, C, CP, LO, HI, E)                                                                \
+#define HAF_TRY_REG(P, Q, R, C, CP, LO, HI)                                                                   \
     if (s > LO && s <= HI) {                                                                                  \
         constexpr int W = RegShape<P, Q, R, C>::W;                                                            \
         int grid = (count + W - 1) / W;                                                                       \
         if (grid > grid_waves) grid = grid_waves;                                                             \
-        if (loops) hipLaunchKernelGGL((k_coef_reg<P, Q, R, C, CP, true, E>), dim3(grid), dim3(64), 0, st, A,  \
+        if (loops) hipLaunchKernelGGL((k_coef_reg<P, Q, R, C, CP, true>), dim3(grid), dim3(64), 0, st, A,     \
                                       lda, N, m, rank0, count, masks, d_exp, coef, cstride);                  \
-        else hipLaunchKernelGGL((k_coef_reg<P, Q, R, C, CP, false, E>), dim3(grid), dim3(64), 0, st, A, lda,  \
+        else hipLaunchKernelGGL((k_coef_reg<P, Q, R, C, CP, false>), dim3(grid), dim3(64), 0, st, A, lda,     \
                                 N, m, rank0, count, masks, d_exp, coef, cstride);                             \
         return hipGetLastError();                                                                             \
     }
-#define HAF_TRY_REG_H(P, Q, R, C, CP, LO, HI) HAF_TRY_REG(P, Q, R, C, CP, LO, HI, false)
-#define HAF_TRY_REG_EL(P, Q, R, C, CP, LO, HI) HAF_TRY_REG(P, Q, R, C, CP, LO, HI, true)
-    if (elim) { HAF_REG_NARROW(HAF_TRY_REG_EL) }
-    if (wide) { HAF_REG_WIDE(HAF_TRY_REG_H) }
-    HAF_REG_NARROW(HAF_TRY_REG_H)
-#undef HAF_TRY_REG_EL
-#undef HAF_TRY_REG_H
+    HAF_REG_TABLE(HAF_TRY_REG)
 #undef HAF_TRY_REG
     return hipErrorInvalidValue;
 }

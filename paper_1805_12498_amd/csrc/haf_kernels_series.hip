@@ -62,9 +62,11 @@ __global__ __launch_bounds__(kSeriesBlock) void k_series(const double2* __restri
     block_partial(sign, f, partials + 4 * (slot0 + blockIdx.x));
 }
 
-// Same-size matrices of a batch (N <= 16): the workgroup finds its chunk by a
-// binary search over the launch's chunk table, then as k_series.
-template <int N, bool LOOPS>
+// Matrices of a batch (every N <= 16): the workgroup finds its chunk by a
+// binary search over the launch's chunk table, then as k_series with the
+// chunk's own N (the series body gives bitwise the same term for a given N
+// whatever its compile-time bound).
+template <bool LOOPS>
 __global__ __launch_bounds__(kSeriesBlock) void k_series_group(const GroupChunk* __restrict__ chunks, int nchunks,
                                                                const double2* __restrict__ coef,
                                                                double* __restrict__ partials) {
@@ -79,7 +81,7 @@ __global__ __launch_bounds__(kSeriesBlock) void k_series_group(const GroupChunk*
     const int lb = blk - ch.gstart;
     const int t = lb * kSeriesBlock + threadIdx.x;
     double2 f = cz();
-    if (t < ch.count) f = subset_series_upto<N, LOOPS>(coef + ch.coff, ch.count, t, N);
+    if (t < ch.count) f = subset_series_upto<16, LOOPS>(coef + ch.coff, ch.count, t, ch.N);
     block_partial(ch.sign, f, partials + 4 * (ch.slot + lb));
 }
 
@@ -121,22 +123,17 @@ static const SeriesMultiFn g_series_multi[17][2] = {
 };
 #undef HAF_SM
 
-using SeriesGroupFn = void (*)(const GroupChunk*, int, const double2*, double*);
-#define HAF_SG(NN) { k_series_group<NN, false>, k_series_group<NN, true> },
-static const SeriesGroupFn g_series_group[17][2] = {
-    { nullptr, nullptr },
-    HAF_SG(1) HAF_SG(2) HAF_SG(3) HAF_SG(4) HAF_SG(5) HAF_SG(6) HAF_SG(7) HAF_SG(8)
-    HAF_SG(9) HAF_SG(10) HAF_SG(11) HAF_SG(12) HAF_SG(13) HAF_SG(14) HAF_SG(15) HAF_SG(16)
-};
-#undef HAF_SG
-
 int group_series_blocks(int count) { return (count + kSeriesBlock - 1) / kSeriesBlock; }
 
-hipError_t launch_series_group(int N, bool loops, int blocks, hipStream_t st, const GroupChunk* chunks, int nchunks,
+hipError_t launch_series_group(bool loops, int blocks, hipStream_t st, const GroupChunk* chunks, int nchunks,
                                const double2* coef, double* partials) {
-    if (N < 1 || N > 16 || nchunks < 1 || blocks < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(g_series_group[N][loops ? 1 : 0], dim3(blocks), dim3(kSeriesBlock), 0, st, chunks, nchunks,
-                       coef, partials);
+    if (nchunks < 1 || blocks < 1) return hipErrorInvalidValue;
+    if (loops)
+        hipLaunchKernelGGL(k_series_group<true>, dim3(blocks), dim3(kSeriesBlock), 0, st, chunks, nchunks, coef,
+                           partials);
+    else
+        hipLaunchKernelGGL(k_series_group<false>, dim3(blocks), dim3(kSeriesBlock), 0, st, chunks, nchunks, coef,
+                           partials);
     return hipGetLastError();
 }
 
@@ -194,12 +191,13 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
     reduce_partials_block(partials, nslots, out_dd, out, d_exp ? *d_exp : 0, N);
 }
 
-// One workgroup per matrix of a same-size group (the single-matrix reduction).
+// One workgroup per matrix of a batch (the single-matrix reduction).
 __global__ __launch_bounds__(256) void k_reduce_group(const GroupItem* __restrict__ items,
                                                        const double* __restrict__ partials,
-                                                       const int* __restrict__ exps, int N) {
+                                                       const int* __restrict__ exps) {
     const GroupItem it = items[blockIdx.x];
-    reduce_partials_block(partials + 4 * it.slot_base, it.nslots, nullptr, it.out, exps[blockIdx.x], N);
+    if (it.cval != kGroupComputed) return;    // written by the prologue
+    reduce_partials_block(partials + 4 * it.slot_base, it.nslots, it.out_dd, it.out, exps[blockIdx.x], it.n / 2);
 }
 
 // Exponent of the exact input scaling.  With f the largest |Re|, |Im| of an
@@ -234,12 +232,22 @@ __global__ __launch_bounds__(256) void k_prescale(const double2* __restrict__ A,
     if (threadIdx.x == 0) *d_exp = e;
 }
 
-// One workgroup per matrix of a same-size group: the dense padded copy of an
-// odd-n loop hafnian (isolated vertex of loop weight 1, as the pad kernel
-// builds it), and the exponent from the caller's matrix (padding adds only
-// zeros off the diagonal, so the exponent is that of the padded matrix).
+// One workgroup per matrix of a batch: a constant result (n = 0, odd-n haf),
+// or the dense padded copy of an odd-n loop hafnian (isolated vertex of loop
+// weight 1, as the pad kernel builds it) and the exponent from the caller's
+// matrix (padding adds only zeros off the diagonal, so the exponent is that of
+// the padded matrix).
 __global__ __launch_bounds__(256) void k_group_prologue(const GroupItem* __restrict__ items, int* __restrict__ exps) {
     const GroupItem it = items[blockIdx.x];
+    if (it.cval != kGroupComputed) {
+        if (threadIdx.x == 0) {
+            const double v = it.cval == kGroupConstOne ? 1.0 : 0.0;
+            if (it.out) *it.out = make_double2(v, 0.0);
+            if (it.out_dd) { it.out_dd[0] = v; it.out_dd[1] = 0.0; it.out_dd[2] = 0.0; it.out_dd[3] = 0.0; }
+            exps[blockIdx.x] = 0;
+        }
+        return;
+    }
     if (it.A != it.src) {
         double2* dst = const_cast<double2*>(it.A);
         for (int e = threadIdx.x; e < it.n * it.n; e += 256) {
@@ -351,9 +359,9 @@ hipError_t launch_group_prologue(hipStream_t st, const GroupItem* items, int nit
 }
 
 hipError_t launch_reduce_group(hipStream_t st, const GroupItem* items, int nitems, const double* partials,
-                               const int* exps, int N) {
+                               const int* exps) {
     if (nitems < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_group, dim3(nitems), dim3(256), 0, st, items, partials, exps, N);
+    hipLaunchKernelGGL(k_reduce_group, dim3(nitems), dim3(256), 0, st, items, partials, exps);
     return hipGetLastError();
 }
 

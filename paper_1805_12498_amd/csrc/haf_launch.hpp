@@ -15,12 +15,10 @@ hipError_t launch_coef_lds(int smax, bool loops, int grid, hipStream_t st, const
                            int64_t cstride);
 
 // Register-tiled coefficient kernel for subsets of s <= reg_max_s() rows (same
-// outputs).  grid_waves bounds the number of one-wave workgroups.  elim selects
-// the Hessenberg reduction by elimination with exchanges (default layouts only),
-// otherwise Householder reflections (wide: one wave per matrix above s = 16).
+// outputs).  grid_waves bounds the number of one-wave workgroups.
 hipError_t launch_coef_reg(int s, bool loops, int grid_waves, hipStream_t st, const double2* A, int lda, int N,
                            int m, uint64_t rank0, int count, const uint32_t* masks, const int* d_exp,
-                           double2* coef, int64_t cstride, bool wide, bool elim);
+                           double2* coef, int64_t cstride);
 int reg_max_s();
 
 // Several chunks of one matrix in one launch (each chunk: one size class m,
@@ -51,42 +49,54 @@ int reg_layout_index(int s);
 hipError_t launch_series_multi(int N, bool loops, hipStream_t st, const double2* coef, double* partials,
                                MultiChunks mc);
 
-// Same-size matrices of a batch in shared launches.  Matrix j of a group is
-// items[j]; chunk c of a launch covers subsets 0..count-1 of size class m of
-// matrix `item` (N <= 16: one chunk per class), owns the workgroups gstart ..
-// (next chunk's gstart or the grid) - 1, keeps its coefficients at coef + coff
-// (stride count) and, for the series, writes partial slots slot, slot + 1, ...
-// Every matrix's coefficients, partial slots and reduction are those of the
-// single-matrix path, so its result is bitwise the same.
+// Matrices of a batch in shared launches (any mix of sizes n <= 32 after the
+// odd-n padding).  Chunk c of a launch covers subsets rank0 .. rank0 + count - 1
+// of size class m of matrix `item` (which has N pairs), owns the workgroups
+// gstart .. (next chunk's gstart or the grid) - 1, keeps its coefficients at
+// coef + coff (stride count) and, for the series, writes partial slots slot,
+// slot + 1, ...  Every matrix's coefficients, partial slots and reduction are
+// those of the single-matrix path, so its result is bitwise the same.
+constexpr int kGroupComputed = -1;       // GroupItem::cval of a matrix the kernels compute
+constexpr int kGroupConstZero = 0;       // haf of odd n
+constexpr int kGroupConstOne = 1;        // n = 0
 struct GroupItem {
     const double2* A;                    // matrix the kernels read (the dense copy for odd-n loop hafnians)
     const double2* src;                  // caller's matrix; the prologue pads it into A when they differ
-    double2* out;                        // result
+    double2* out;                        // result, or null
+    double* out_dd;                      // double-double result (re_hi, re_lo, im_hi, im_lo), or null
     int n, lda, src_n, src_lda;
+    int cval, pad_;                      // kGroupComputed, or the constant result the prologue writes
     int64_t slot_base;                   // the matrix's first partial slot
     int64_t nslots;                      // its partial slots
 };
 struct GroupChunk {
     int item, m, count, gstart;
+    int N, pad_;
+    uint64_t rank0;
     int64_t coff, slot;
     double sign;                         // (-1)^(N - m)
 };
-// One workgroup per matrix: pad odd-n loop hafnians into A, exponent of the
-// exact input scaling into exps[j] (as the prescale kernel computes it).
+// One workgroup per matrix: write constant results, pad odd-n loop hafnians
+// into A, exponent of the exact input scaling into exps[j] (as the prescale
+// kernel computes it).
 hipError_t launch_group_prologue(hipStream_t st, const GroupItem* items, int nitems, int* exps);
-// Coefficients of the chunks of one launch (all s = 2m in the range of the
-// default layout named by s_max); blocks = the launch's grid, as planned by the
-// host with group_coef_blocks.
-int group_coef_blocks(int s_max, int count);
-hipError_t launch_coef_reg_group(int s_max, bool loops, int blocks, hipStream_t st, const GroupItem* items,
-                                 const GroupChunk* chunks, int nchunks, int N, const int* exps, double2* coef);
-// Series + signed block partials of the chunks of one launch (N <= 16).
+// Coefficients of the chunks of one launch, all served by register layout
+// `layout` (an index into the layout table; every chunk's s = 2m must lie in
+// the layout's range (SM - 8, SM]); blocks = the launch's grid, as planned by
+// the host with group_coef_blocks.
+int reg_layout_count();
+int reg_layout_sm(int layout);           // largest s of the layout
+int reg_layout_groups(int layout);       // matrices per wave
+int group_coef_blocks(int layout, int count, int span);
+hipError_t launch_coef_reg_group(int layout, bool loops, int blocks, hipStream_t st, const GroupItem* items,
+                                 const GroupChunk* chunks, int nchunks, const int* exps, double2* coef);
+// Series + signed block partials of the chunks of one launch (every N <= 16).
 int group_series_blocks(int count);
-hipError_t launch_series_group(int N, bool loops, int blocks, hipStream_t st, const GroupChunk* chunks, int nchunks,
+hipError_t launch_series_group(bool loops, int blocks, hipStream_t st, const GroupChunk* chunks, int nchunks,
                                const double2* coef, double* partials);
 // One workgroup per matrix: its partials reduced as the single-matrix path does.
 hipError_t launch_reduce_group(hipStream_t st, const GroupItem* items, int nitems, const double* partials,
-                               const int* exps, int N);
+                               const int* exps);
 
 // Exponent e of the exact input scaling (off-diagonal by 2^-2e, diagonal by
 // 2^-e; the result is multiplied back by 2^(2eN)), written to *d_exp.
@@ -108,26 +118,3 @@ hipError_t launch_bipartite(hipStream_t st, const double2* W, int n, int ldw, do
 
 }  // namespace hafgpu
 
-#include "haf_batch.hpp"
-
-namespace hafgpu {
-
-// Persistent batched kernel.  Variants (layout table, waves per SIMD, series
-// bound): 0 = (0, 2, 16), 1 = (1, 2, 16), 2 = (2, 1, 24), 3 = (0, 1, 16),
-// 4 = (0, 2, 24), 5 = (1, 2, 24), 6 = (0, 1, 24).  Table 0: the default layouts
-// up to s = 32; 1: one wave per matrix above s = 16, up to 32; 2: s = 34..48.
-int batch_group_count(int table, int s);       // matrices per wave of table's layout for s rows
-int batch_variant_table(int v);
-int batch_variant_nmax(int v);
-int batch_coef_per_wave(int v);                // coefficient scratch per wave (complex values)
-int batch_waves_per_cu(int v);                 // resident one-wave workgroups per CU
-const void* batched_kernel16(int v);
-bool launch_batched16(int v, int grid, hipStream_t st, const BatchItem* items, const BatchClass* classes, int ncls,
-                      int nchunks, int* cursor, int* done, const int* exps, double* partials, double2* coefscr);
-hipError_t launch_batch_prologue(hipStream_t st, const BatchItem* items, const int* new_items, int nnew, int* exps,
-                                 int* done, int* cursor);
-hipError_t launch_batched(int v, int grid, hipStream_t st, const BatchItem* items, const BatchClass* classes,
-                          int ncls, int nchunks, int* cursor, int* done, const int* exps, double* partials,
-                          double2* coefscr);
-
-}  // namespace hafgpu

@@ -257,7 +257,7 @@ int launch_coef_chunk(int dev, const double2* dA, int lda, int N, int m, uint64_
     hipError_t e;
     if (g_kernel_path != 1 && s <= reg_max_s())
         e = launch_coef_reg(s, loops, device_cus(dev) * 16, st, dA, lda, N, m, rank0, count, masks, d_exp, coef,
-                            cstride, g_kernel_path == 3, g_kernel_path == 4);
+                            cstride);
     else
         e = launch_coef_lds(s, loops, coef_grid(dev, count), st, dA, lda, N, m, rank0, count, masks, d_exp, coef,
                             cstride);
@@ -636,7 +636,7 @@ int haf_release_workspaces(void) {
 
 int haf_set_kernel_path(int path) {
     clear_error();
-    if (path < 0 || path > 4) return set_error(HAF_E_INVALID_ARG, "kernel path %d not in 0..4", path);
+    if (path < 0 || path > 2) return set_error(HAF_E_INVALID_ARG, "kernel path %d not in 0..2", path);
     set_kernel_path(path);
     return HAF_OK;
 }

@@ -57,8 +57,13 @@ def ryser_entry(W, prec, what):
 
 
 def exact_entry(A, loops, what, nprimes):
-    v, sec = oracle.exact_int(A, loops, nprimes=nprimes)
-    return {"what": what, "route": "formula over F_p + CRT", "exact": str(v), "seconds": sec}
+    # Many more threads than cores: the static split of the mask range gives the
+    # ranges with high leading bits larger subsets, so fine ranges balance the load.
+    # The sum mod p is exact, so the thread count does not change the value.
+    threads = 8 * (os.cpu_count() or 1)
+    v, sec = oracle.exact_int(A, loops, nprimes=nprimes, threads=threads)
+    return {"what": what, "route": "formula over F_p + CRT", "primes": nprimes + 1, "exact": str(v),
+            "seconds": sec, "threads": threads}
 
 
 JOBS = {

@@ -1,88 +1,143 @@
-"""Host-side plan of the batched path (no GPU): every subset of every matrix is
-covered exactly once, partial slots are distinct per matrix, chunk numbering is
-contiguous per launch, and the largest chunks come first."""
+"""Host-side plan of the shared batched launches (no GPU): every subset size
+class of every matrix up to 32 rows is covered by exactly one coefficient chunk
+and one series chunk with the same coefficient area, partial slots are those of
+the single-matrix plan and distinct across matrices, workgroup numbering is
+contiguous per launch, every chunk sits in a launch whose layout serves its
+subset size, coefficient areas of a launch are disjoint and within budget."""
 import math
 
+import numpy as np
 import pytest
 
 from gen import inputs as gi
+
+SERIES_BLOCK = 256
+# (largest s, matrices per wave) of the register layouts, in table order
+LAYOUT_SM = [8, 12, 16, 20, 24, 28, 32, 40, 48]
+LAYOUT_W = [4, 4, 4, 2, 2, 2, 2, 1, 1]
 
 
 @pytest.fixture(scope="module")
 def hg():
     import paper_1805_12498_amd as hg
     hg.load()
-    return hg
+    yield hg
+    hg.set_batched_config()
 
 
-def check_plan(hg, sizes, kinds):
-    cls, nchunks, variant = hg.batched_plan(sizes, kinds)
-    covered = {}
-    slots = {}
-    launch_chunks = [0, 0]
-    launch = 0
-    prev_cost = math.inf
-    for item, m, cap, total, j0, base, slot_base, nslots in cls:
-        if 2 * m <= 32 and launch == 0:
-            launch, prev_cost = 1, math.inf
-        assert base == launch_chunks[launch]                  # contiguous numbering
-        # default layout table: 4 matrices per wave up to 16 rows, 2 up to 32, then 1
-        W = 4 if 2 * m <= 16 else (2 if 2 * m <= 32 else 1)
-        cost = -(-cap // W) * (2 * m) ** 3
-        assert cost <= prev_cost                               # largest chunks first
-        prev_cost = cost
-        n_here = (total + cap - 1) // cap - j0
-        launch_chunks[launch] += n_here
-        assert 1 <= cap <= 64 and j0 == 0
-        N = sizes[item] // 2 + (sizes[item] % 2)
-        assert total == math.comb(N, m)
-        covered[(item, m)] = covered.get((item, m), 0) + total
-        for j in range(n_here):
-            s = slot_base + j
-            assert 0 <= s < nslots
-            assert (item, s) not in slots
-            slots[(item, s)] = True
-    assert sum(launch_chunks) == nchunks
-    for t, n in enumerate(sizes):
-        if n == 0 or (n % 2 == 1 and kinds[t] == 0) or n + (n % 2) > 48:
-            assert not any(k[0] == t for k in covered)
-            continue
-        N = (n + (n % 2)) // 2
-        assert sum(v for (i, m), v in covered.items() if i == t) == 2 ** N - 1
-        # every slot of the item is used
-        item_slots = [s for (i, s) in slots if i == t]
-        assert sorted(item_slots) == list(range(len(item_slots)))
-    return cls, nchunks, variant
+def single_plan_slots(n_eff):
+    """Slots of the single-matrix plan: size classes m = 1..N in order, one slot per
+    series block of 256 subsets (one chunk per class for N <= 16)."""
+    N = n_eff // 2
+    slot0, s = {}, 0
+    for m in range(1, N + 1):
+        slot0[m] = s
+        s += -(-math.comb(N, m) // SERIES_BLOCK)
+    return slot0, s
 
 
-def test_plan_small_mixed(hg):
-    sizes = list(range(0, 15)) * 2
-    kinds = [0] * 15 + [1] * 15
-    check_plan(hg, sizes, kinds)
+def check_plan(hg, sizes, kinds, table, span, budget_mb):
+    hg.set_batched_config(table=table, span=span, coef_budget_mb=budget_mb)
+    launches, chunks = hg.batched_plan(sizes, kinds)
+    expect = {}
+    base = {}
+    nxt = 0
+    for t, (n, k) in enumerate(zip(sizes, kinds)):
+        if n == 0 or (n % 2 and k == 0):
+            continue                                   # constants: prologue only
+        ne = n + (n % 2)
+        assert ne <= 32
+        slot0, total = single_plan_slots(ne)
+        base[t] = nxt
+        nxt += total
+        for m in range(1, ne // 2 + 1):
+            expect[(t, m)] = slot0[m]
+    seen = {0: {}, 1: {}}
+    budget = budget_mb * (1 << 20) // 16
+    assert len(launches) % 2 == 0
+    for li, (what, lay, loops, blocks, first, nch, celems, sm) in enumerate(launches):
+        assert what == li % 2                          # coefficient launch, then its series launch
+        assert sm == LAYOUT_SM[lay]
+        rows = chunks[first:first + nch]
+        g = 0
+        areas = []
+        for item, m, count, gstart, coff, slot, N, rank0 in rows:
+            assert gstart == g                         # contiguous workgroups
+            if what == 0:
+                assert sm - 8 < 2 * m <= sm            # the layout serves this subset size
+                if table == 1:
+                    assert sm % 8 == 0
+                else:
+                    assert lay == next(i for i, x in enumerate(LAYOUT_SM) if 2 * m <= x)
+                w = LAYOUT_W[lay] * span
+                g += -(-count // w)
+            else:
+                g += -(-count // SERIES_BLOCK)
+            assert kinds[item] == loops
+            ne = sizes[item] + (sizes[item] % 2)
+            assert N == ne // 2 and rank0 == 0 and count == math.comb(N, m)
+            assert slot == base[item] + expect[(item, m)]
+            key = (item, m)
+            assert key not in seen[what], key
+            seen[what][key] = (li // 2, coff)
+            ncoef = 2 * N if loops else N
+            areas.append((coff, coff + count * ncoef))
+        assert g == blocks
+        areas.sort()
+        for (a0, a1), (b0, b1) in zip(areas, areas[1:]):
+            assert a1 <= b0                            # disjoint coefficient areas
+        assert areas[-1][1] == celems
+        assert celems <= budget or nch == 1
+    # both launches of a pair see the same chunks at the same coefficient offsets
+    assert seen[0] == seen[1]
+    assert set(seen[0]) == set(expect)
+    return launches
 
 
-def test_plan_gbs_batch(hg):
-    mats = gi.gbs_batch(256, seed=gi.SEED_BATCH)
+def test_gbs_batch_plan(hg):
+    mats = gi.gbs_batch(512, seed=gi.SEED_BATCH)
     sizes = [m.shape[0] for m in mats]
-    cls, nchunks, variant = check_plan(hg, sizes, [1] * len(sizes))
-    assert variant in (0, 1, 3)                # all items up to 32 rows: series bound 16
-    assert all(2 * c[1] <= 32 for c in cls)
+    kinds = [1] * len(mats)
+    for table, span in ((0, 1), (0, 4), (1, 8)):
+        launches = check_plan(hg, sizes, kinds, table, span, 8192)
+        # one launch pair per layout that the batch uses: 9 or 4 stages at most
+        assert len(launches) // 2 <= (9 if table == 0 else 4)
 
 
-def test_plan_with_large_items(hg):
-    sizes = [8, 40, 46, 50, 33]
-    kinds = [1, 0, 1, 0, 1]
-    cls, nchunks, variant = check_plan(hg, sizes, kinds)
-    assert variant in (4, 5, 6)                # items above 32 rows: series bound 24
-    big = [c for c in cls if 2 * c[1] > 32]
-    assert big and all(2 * c[1] > 32 for c in cls[:len(big)])    # the large-subset launch comes first
-    assert not any(c[0] == 3 for c in cls)      # n = 50 goes to the single-matrix path
+def test_mixed_plan_small_budget(hg):
+    sizes, kinds = [], []
+    for n in range(0, 33):
+        for k in (0, 1):
+            sizes.append(n)
+            kinds.append(k)
+    sizes += [32] * 6 + [31, 33, 40]
+    kinds += [1] * 6 + [1, 0, 1]
+    # 33 (haf, odd: constant) stays in the shared launches; 40 does not
+    big = [t for t, n in enumerate(sizes) if n + (n % 2) * kinds[t] > 32 and not (n % 2 and kinds[t] == 0)]
+    keep = [t for t in range(len(sizes)) if t not in big]
+    launches = check_plan(hg, [sizes[t] for t in keep], [kinds[t] for t in keep], 0, 2, 64)
+    assert len(launches) > 2 * 9                       # the 64 MiB budget cuts some stages
+    check_plan(hg, [sizes[t] for t in keep], [kinds[t] for t in keep], 1, 64, 64)
 
 
-def test_plan_chunk_sizes(hg):
-    """Subsets per chunk shrink as (16/s)^3 (group_work 16 per matrix slot at 16 rows),
-    between one per matrix slot and 64 per wave."""
-    cls, _, _ = check_plan(hg, [32], [1])
-    cap = {2 * c[1]: c[2] for c in cls}
-    assert cap[16] == 64 and cap[8] == 64 and cap[2] == 64
-    assert cap[24] == 2 * (16 * 4096 // 24 ** 3) and cap[32] == 2 * 2
+def test_plan_lists_only_shared_matrices(hg):
+    hg.set_batched_config()
+    launches, chunks = hg.batched_plan([34, 40, 12, 0, 7], [0, 1, 0, 1, 0])
+    items = set(int(i) for i in chunks[:, 0])
+    assert items == {2}
+
+
+def test_plan_rejects_bad_items(hg):
+    from paper_1805_12498_amd._native import HafError
+    with pytest.raises(HafError, match="INVALID_ARG"):
+        hg.batched_plan([4, 66], [0, 0])
+    with pytest.raises(HafError, match="INVALID_ARG"):
+        hg.batched_plan([4], [3])
+    with pytest.raises(HafError, match="INVALID_ARG"):
+        hg.set_batched_config(span=0)
+    with pytest.raises(HafError, match="INVALID_ARG"):
+        hg.set_batched_config(streams=8)
+    hg.set_batched_config()
+    assert hg.batched_config() == {"table": 0, "span": 4, "streams": 4, "grouped": 1, "coef_budget_mb": 8192}
+    launches, chunks = hg.batched_plan([], [])
+    assert len(launches) == 0 and len(chunks) == 0

@@ -1,11 +1,14 @@
 """GPU tests of the batched path (haf_batched_c128) through the C ABI.
 
-The batch is spread over a pool of streams, each filled with the
-single-matrix path.  Checks: results against the CPU oracle (brute force at
-small n, the formula in double-double at mid n), bitwise equality with the
-single-matrix path and independence of a result from the rest of the batch
-and from the stream count, bitwise reproducibility, the constant and padded
-edge cases, errors and the autotuner.
+Matrices up to 32 rows share launches (one coefficient and one series launch
+per register layout and kind, one reduction); larger ones run the
+single-matrix path on a pool of streams.  Checks: results against the CPU
+oracle (brute force at small n, the formula in double-double at mid n), bitwise
+equality with the single-matrix path and independence of a result from the
+rest of the batch and from every configuration knob (layout table, subsets
+per lane group, coefficient budget, stream count), bitwise reproducibility,
+the constant and padded edge cases, the double-double output, errors and the
+autotuner.
 """
 import numpy as np
 import pytest
@@ -23,10 +26,10 @@ C_TOL = 64.0
 def hg():
     import paper_1805_12498_amd as hg
     hg.load()
-    hg.set_batched_config(streams=8)
+    hg.set_batched_config()
     print("device:", hg.device_info(), flush=True)
     yield hg
-    hg.set_batched_config(streams=8)
+    hg.set_batched_config()
 
 
 def rel(a, b):
@@ -76,20 +79,20 @@ def test_small_mixed_vs_brute_force(hg):
             assert rel(g, ref) < 1e-12, (A.shape[0], kind, g, ref)
 
 
-@pytest.mark.parametrize("streams", [1, 4, 16])
-def test_gbs_batch_vs_oracle_and_plain(hg, streams):
+@pytest.mark.parametrize("table,span", [(0, 1), (0, 4), (1, 16)])
+def test_gbs_batch_vs_oracle_and_plain(hg, table, span):
     """GBS-style loop hafnians n in [8, 32] (the batched workload's construction):
     bitwise the single-matrix path on all, the oracle (double-double formula) on a sample."""
-    hg.set_batched_config(streams=streams)
+    hg.set_batched_config(table=table, span=span)
     mats = gi.gbs_batch(48, seed=gi.SEED_BATCH + 1)
     kinds = [1] * len(mats)
     got = run_batch(hg, mats, kinds)
     for t, A in enumerate(mats):
-        assert got[t] == run_plain(hg, A, 1), (streams, t, A.shape[0])
+        assert got[t] == run_plain(hg, A, 1), (table, span, t, A.shape[0])
     for t in range(0, len(mats), 8):
         ref, kappa = oracle.formula(mats[t], True, prec="dd", want_kappa=True)
-        assert ref.relerr(got[t]) <= max(1e-12, C_TOL * EPS * kappa), (streams, t, mats[t].shape[0])
-    hg.set_batched_config(streams=8)
+        assert ref.relerr(got[t]) <= max(1e-12, C_TOL * EPS * kappa), (table, span, t, mats[t].shape[0])
+    hg.set_batched_config()
 
 
 def test_alone_equals_in_mix_bitwise(hg):
@@ -149,10 +152,11 @@ def test_errors(hg):
 
 
 def test_grouped_vs_ungrouped_bitwise(hg):
-    """Same-size matrices in shared launches (grouped, the default) against every matrix
-    on its own launches: bitwise equal, over constants, odd n, padded odd-n loop hafnians,
-    sizes past the grouped range (n > 32) and a group of n = 32 loop hafnians large enough
-    to be split into two coefficient sub-batches."""
+    """Shared launches (grouped, the default) against every matrix on its own launches:
+    bitwise equal, over constants, odd n, padded odd-n loop hafnians, sizes past the
+    shared range (n > 32), and a stage of n = 32 loop hafnians large enough to be cut into
+    several launch pairs by a small coefficient budget; under both layout tables, several
+    subsets-per-lane-group settings and 1 or 4 streams."""
     mats, kinds = [], []
     for n in list(range(0, 34)) + [36, 40]:
         for kind in (0, 1):
@@ -163,17 +167,45 @@ def test_grouped_vs_ungrouped_bitwise(hg):
         kinds.append(1)
     mats.append(rand_sym(31, 6100))
     kinds.append(1)
+    runs = {}
     try:
-        hg.set_batched_config(streams=4, grouped=1)
-        g = run_batch(hg, mats, kinds)
         hg.set_batched_config(streams=4, grouped=0)
         u = run_batch(hg, mats, kinds)
+        for table, span, streams, budget in ((0, 4, 4, 8192), (1, 1, 1, 64), (0, 16, 2, 64), (1, 64, 4, 8192)):
+            hg.set_batched_config(table=table, span=span, streams=streams, coef_budget_mb=budget)
+            runs[(table, span, streams, budget)] = run_batch(hg, mats, kinds)
     finally:
-        hg.set_batched_config(streams=8)
-    for t in range(len(mats)):
-        assert g[t] == u[t], (t, mats[t].shape[0], kinds[t], g[t], u[t])
+        hg.set_batched_config()
+    for key, g in runs.items():
+        for t in range(len(mats)):
+            assert g[t] == u[t], (key, t, mats[t].shape[0], kinds[t], g[t], u[t])
     for t in (0, 5, 17, 40, 60, 71):
-        assert g[t] == run_plain(hg, mats[t], kinds[t]), (t, mats[t].shape[0])
+        assert u[t] == run_plain(hg, mats[t], kinds[t]), (t, mats[t].shape[0])
+
+
+def test_double_double_output(hg):
+    """haf_batched_c128x2: the (hi, lo) pairs of each result; hi + lo rounds to the
+    complex128 result bitwise, and the pair equals the single-matrix x2 result."""
+    import torch
+    mats = gi.gbs_batch(40, seed=12) + [rand_sym(0, 1), rand_sym(5, 2), rand_sym(36, 3)]
+    kinds = [t % 2 for t in range(len(mats))]
+    flat, offs, sizes = gi.pack(mats)
+    dA = torch.from_numpy(flat).cuda()
+    out2 = torch.zeros((len(mats), 4), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    hg.batched_dev(dA.data_ptr(), offs, sizes, np.asarray(kinds, np.uint8), out2.data_ptr(), st, x2=True)
+    torch.cuda.synchronize()
+    got2 = out2.cpu().numpy()
+    got = run_batch(hg, mats, kinds)
+    one = torch.zeros(4, dtype=torch.float64, device="cuda")
+    for t, A in enumerate(mats):
+        assert complex(got2[t, 0] + got2[t, 1], got2[t, 2] + got2[t, 3]) == got[t], t
+        if t % 7 == 0 or t >= len(mats) - 3:
+            n = A.shape[0]
+            dM = torch.from_numpy(np.ascontiguousarray(A) if n else np.zeros(1, complex)).cuda()
+            hg.haf_dev(dM.data_ptr(), n, max(n, 1), one.data_ptr(), st, kind=kinds[t], x2=True)
+            torch.cuda.synchronize()
+            assert np.array_equal(one.cpu().numpy(), got2[t]), t
 
 
 def test_autotuner(hg):
@@ -186,9 +218,9 @@ def test_autotuner(hg):
     cfg, ms = hg.batched_tune(dA.data_ptr(), offs, sizes, kinds, out.data_ptr(),
                               torch.cuda.current_stream().cuda_stream)
     print("tuned:", cfg, "%.3f ms" % ms, flush=True)
-    assert hg.batched_config() == cfg and ms > 0 and cfg["streams"] in (1, 2, 4, 8, 16)
-    assert cfg["grouped"] in (0, 1)
+    assert hg.batched_config() == cfg and ms > 0 and cfg["streams"] in (1, 2, 4)
+    assert cfg["grouped"] in (0, 1) and cfg["table"] in (0, 1) and 1 <= cfg["span"] <= 16
     tuned = out.cpu().numpy()
     again = run_batch(hg, mats, kinds)
     assert np.array_equal(tuned, again)
-    hg.set_batched_config(streams=8)
+    hg.set_batched_config()
