@@ -111,6 +111,23 @@ int lhaf_c128_dev(const haf_cplx* dA, int n, int lda, haf_cplx* d_out, void* str
 int haf_c128x2_dev(const haf_cplx* dA, int n, int lda, int kind, haf_cplx2* d_out, void* stream);
 
 /*
+ * Allocation-free variant of haf_c128x2_dev, for callers that cannot allocate
+ * device memory (code under stream or graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, same launch sequence and
+ * bitwise the same result as haf_c128x2_dev; every work buffer (exponent,
+ * padded odd-n matrix, partial slots, coefficients) comes from one fixed
+ * 80 MiB array in device memory that the library holds on each device it runs
+ * on until the process ends, so the call performs no allocation of any kind.
+ * Limit: n <= 56 (after padding an odd n for lhaf); larger n return
+ * HAF_E_TOO_LARGE (the partial slots of n = 58 alone exceed the array).  Every
+ * call on one device uses the same array, so calls that overlap on a device
+ * (on different streams, or from different threads without ordering) race
+ * and give wrong results; calls ordered on one stream are safe.  The array
+ * keeps the last call's contents; nothing in it needs clearing between calls.
+ */
+int haf_c128x2_dev_noalloc(const haf_cplx* dA, int n, int lda, int kind, haf_cplx2* d_out, void* stream);
+
+/*
  * The unsigned terms f(Z) (Sec. 3.3, Eq. haffinal without the outer sum) for
  * the subsets given as bit masks over the n/2 pairs (bit i = pair (2i, 2i+1)).
  * d_masks: device uint32[count]; d_terms: device haf_cplx[count].  Exposes the

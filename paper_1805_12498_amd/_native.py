@@ -29,6 +29,7 @@ EXPORTS = (
     "haf_server_submit", "haf_server_poll", "haf_server_drain", "haf_server_destroy", "haf_now",
     "haf_profile_enable", "haf_profile_read", "haf_batched_get_config", "haf_batched_set_config",
     "haf_batched_tune", "haf_batched_plan", "haf_batched_c128x2", "perm_c128", "perm_c128_dev",
+    "haf_c128x2_dev_noalloc",
 )
 
 
@@ -100,6 +101,7 @@ def load(path: str = LIB_PATH):
         "haf_c128_dev": ([vp, i, i, vp, vp], i),
         "lhaf_c128_dev": ([vp, i, i, vp, vp], i),
         "haf_c128x2_dev": ([vp, i, i, i, vp, vp], i),
+        "haf_c128x2_dev_noalloc": ([vp, i, i, i, vp, vp], i),
         "haf_terms_dev": ([vp, i, i, i, vp, i, vp, vp], i),
         "haf_batched_c128": ([vp, vp, vp, vp, i, vp, vp], i),
         "haf_batched_c128x2": ([vp, vp, vp, vp, i, vp, vp], i),

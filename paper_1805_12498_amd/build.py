@@ -25,6 +25,7 @@ SOURCES = [
     "haf_kernels_lds.hip",
     "haf_kernels_reg.hip",
     "haf_kernels_series.hip",
+    "haf_noalloc.hip",
     "haf_runtime.cpp",
     "haf_batched.cpp",
     "haf_server.cpp",

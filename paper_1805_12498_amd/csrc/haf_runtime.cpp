@@ -523,7 +523,8 @@ const char* haf_version(void) { return "hafgpu 0.1 (gfx950)"; }
 int haf_init(int device) {
     clear_error();
     if (hipSetDevice(device) != hipSuccess) return set_error(HAF_E_DEVICE, "hipSetDevice(%d) failed", device);
-    return ensure_device(nullptr);
+    const int rc = ensure_device(nullptr);
+    return rc ? rc : noalloc_setup(device);
 }
 
 int haf_device_info(char* buf, int buflen) {

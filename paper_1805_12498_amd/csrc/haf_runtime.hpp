@@ -59,5 +59,6 @@ int prof_begin(hipStream_t st, int what, double flops, int64_t subsets);
 void prof_end(int idx, hipStream_t st);
 double coef_model_flops(int s, int N, bool loops);
 void release_batch_workspaces();
+int noalloc_setup(int dev);   // device address of the allocation-free entry point's scratch array
 
 }  // namespace hafgpu
