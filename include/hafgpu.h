@@ -138,6 +138,28 @@ int haf_terms_dev(const haf_cplx* dA, int n, int lda, int kind, const uint32_t* 
                   haf_cplx* d_terms, void* stream);
 
 /*
+ * Exact hafnian / loop hafnian of an integer matrix (row-major int64, leading
+ * dimension lda >= n, exactly symmetric off the diagonal; haf ignores the
+ * diagonal).  Each term f(Z) of the subset sum counts tangles and is an
+ * integer (Sec. 3.2, Eq. Pset), and the route from B = X A_Z to f(Z) needs
+ * only field operations (App. B), so the library runs the whole sum on the GPU
+ * modulo primes p < 2^25 (the largest ones below 2^25) and reconstructs the
+ * integer by Chinese remaindering: enough primes for a product above twice a
+ * bound on |haf| ((n-1)!! max|a_ij|^(n/2); T(n) max(sqrt(max|a_ij|),
+ * max|a_ii|)^n for lhaf), plus one more prime that must agree.  Host pointers,
+ * synchronous.  The value is returned as sign (-1, 0, 1) and magnitude, eight
+ * 32-bit limbs, least significant first.  n = 0 gives 1, odd n gives 0 for
+ * haf and lhaf(A (+) [1]) for lhaf.  Errors: HAF_E_INVALID_ARG,
+ * HAF_E_NOT_SYMMETRIC, HAF_E_TOO_LARGE (n > 64, or a bound that needs more than
+ * ten primes, e.g. n > 56 for dense 0/1 graphs), HAF_E_DEVICE (also if the
+ * check prime disagrees), HAF_E_NOMEM.
+ */
+int haf_exact_i64(const int64_t* A, int n, int lda, int kind, uint32_t* magnitude, int* sign);
+/* The same sum modulo each of the given primes (1..10 of them, each a prime
+ * with n + 1 < p < 2^25; HAF_E_INVALID_ARG otherwise): residues[i] in [0, p_i). */
+int haf_modp_c(const int64_t* A, int n, int lda, int kind, const uint32_t* primes, int nprimes, uint32_t* residues);
+
+/*
  * Batched: count independent hafnians / loop hafnians of uneven sizes (the
  * per-matrix sums of Sec. 3.2, Eq. Pset; the paper names batched small-matrix
  * GPU work as the way forward in its conclusions).  Matrix t is stored densely

@@ -29,7 +29,7 @@ EXPORTS = (
     "haf_server_submit", "haf_server_poll", "haf_server_drain", "haf_server_destroy", "haf_now",
     "haf_profile_enable", "haf_profile_read", "haf_batched_get_config", "haf_batched_set_config",
     "haf_batched_tune", "haf_batched_plan", "haf_batched_c128x2", "perm_c128", "perm_c128_dev",
-    "haf_c128x2_dev_noalloc",
+    "haf_c128x2_dev_noalloc", "haf_exact_i64", "haf_modp_c",
 )
 
 
@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
         "lhaf_c128_dev": ([vp, i, i, vp, vp], i),
         "haf_c128x2_dev": ([vp, i, i, i, vp, vp], i),
         "haf_c128x2_dev_noalloc": ([vp, i, i, i, vp, vp], i),
+        "haf_exact_i64": ([vp, i, i, i, vp, ctypes.POINTER(i)], i),
+        "haf_modp_c": ([vp, i, i, i, vp, i, vp], i),
         "haf_terms_dev": ([vp, i, i, i, vp, i, vp, vp], i),
         "haf_batched_c128": ([vp, vp, vp, vp, i, vp, vp], i),
         "haf_batched_c128x2": ([vp, vp, vp, vp, i, vp, vp], i),
@@ -157,6 +159,46 @@ def haf_host(A, kind: int = KIND_HAF, x2: bool = False):
     fn = lib.haf_c128 if kind == KIND_HAF else lib.lhaf_c128
     check(fn(ctypes.c_void_p(ptr), n, max(n, 1), ctypes.byref(out)))
     return complex(out.re, out.im)
+
+
+def _int_matrix(A):
+    A = np.asarray(A)
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("expected a square matrix")
+    if A.dtype.kind == "c":
+        if np.any(A.imag != 0):
+            raise ValueError("exact hafnians take integer matrices")
+        A = A.real
+    if A.dtype.kind == "f" and np.any(A != np.round(A)):
+        raise ValueError("exact hafnians take integer matrices")
+    return np.ascontiguousarray(A, dtype=np.int64)
+
+
+def haf_exact(A, kind: int = KIND_HAF) -> int:
+    """Exact haf / lhaf of an integer matrix (GPU sum over prime fields + CRT) as a Python int."""
+    A = _int_matrix(A)
+    n = A.shape[0]
+    mag = np.zeros(8, dtype=np.uint32)
+    sign = ctypes.c_int(0)
+    ptr = A.ctypes.data if n else ctypes.addressof(ctypes.c_int64(0))
+    check(load().haf_exact_i64(ctypes.c_void_p(ptr), n, max(n, 1), kind, ctypes.c_void_p(mag.ctypes.data),
+                               ctypes.byref(sign)))
+    v = 0
+    for limb in mag[::-1]:
+        v = (v << 32) | int(limb)
+    return sign.value * v
+
+
+def haf_modp(A, primes, kind: int = KIND_HAF):
+    """haf / lhaf of an integer matrix modulo each prime (GPU), as a list of ints."""
+    A = _int_matrix(A)
+    n = A.shape[0]
+    primes = np.ascontiguousarray(primes, dtype=np.uint32)
+    res = np.zeros(len(primes), dtype=np.uint32)
+    ptr = A.ctypes.data if n else ctypes.addressof(ctypes.c_int64(0))
+    check(load().haf_modp_c(ctypes.c_void_p(ptr), n, max(n, 1), kind, ctypes.c_void_p(primes.ctypes.data),
+                            len(primes), ctypes.c_void_p(res.ctypes.data)))
+    return [int(r) for r in res]
 
 
 def perm_host(W) -> complex:

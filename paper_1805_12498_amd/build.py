@@ -26,9 +26,11 @@ SOURCES = [
     "haf_kernels_reg.hip",
     "haf_kernels_series.hip",
     "haf_noalloc.hip",
+    "haf_kernels_modp.hip",
     "haf_runtime.cpp",
     "haf_batched.cpp",
     "haf_server.cpp",
+    "haf_exact.cpp",
 ]
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
