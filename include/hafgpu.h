@@ -138,6 +138,21 @@ int haf_terms_dev(const haf_cplx* dA, int n, int lda, int kind, const uint32_t* 
                   haf_cplx* d_terms, void* stream);
 
 /*
+ * Per-term double-double precision mode (opt-in): the same route as the
+ * device and host entry points (Householder Hessenberg form, characteristic
+ * polynomial, Newton's identities, exponential series), but every step of each
+ * term f(Z) in complex double-double (about 106 significant bits) instead of
+ * complex double.  The paper's precision ablation (Sec. 4.2) shows that the
+ * precision of the terms, not the outer summation, sets the error of the
+ * alternating sum; with double-double terms the error bound drops from
+ * ~eps64 * kappa to ~eps_dd * kappa (kappa = sum_Z |f(Z)| / |haf|).  About an
+ * order of magnitude more work per term.  Arguments, layout, edge cases and
+ * errors as haf_c128x2_dev / haf_c128x2_host; the result is double-double.
+ */
+int haf_dd_c128x2_dev(const haf_cplx* dA, int n, int lda, int kind, haf_cplx2* d_out, void* stream);
+int haf_dd_c128x2_host(const haf_cplx* A, int n, int lda, int kind, haf_cplx2* out);
+
+/*
  * Exact hafnian / loop hafnian of an integer matrix (row-major int64, leading
  * dimension lda >= n, exactly symmetric off the diagonal; haf ignores the
  * diagonal).  Each term f(Z) of the subset sum counts tangles and is an

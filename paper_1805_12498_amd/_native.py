@@ -29,7 +29,7 @@ EXPORTS = (
     "haf_server_submit", "haf_server_poll", "haf_server_drain", "haf_server_destroy", "haf_now",
     "haf_profile_enable", "haf_profile_read", "haf_batched_get_config", "haf_batched_set_config",
     "haf_batched_tune", "haf_batched_plan", "haf_batched_c128x2", "perm_c128", "perm_c128_dev",
-    "haf_c128x2_dev_noalloc", "haf_exact_i64", "haf_modp_c",
+    "haf_c128x2_dev_noalloc", "haf_exact_i64", "haf_modp_c", "haf_dd_c128x2_dev", "haf_dd_c128x2_host",
 )
 
 
@@ -103,6 +103,8 @@ def load(path: str = LIB_PATH):
         "haf_c128x2_dev": ([vp, i, i, i, vp, vp], i),
         "haf_c128x2_dev_noalloc": ([vp, i, i, i, vp, vp], i),
         "haf_exact_i64": ([vp, i, i, i, vp, ctypes.POINTER(i)], i),
+        "haf_dd_c128x2_dev": ([vp, i, i, i, vp, vp], i),
+        "haf_dd_c128x2_host": ([vp, i, i, i, vp], i),
         "haf_modp_c": ([vp, i, i, i, vp, i, vp], i),
         "haf_terms_dev": ([vp, i, i, i, vp, i, vp, vp], i),
         "haf_batched_c128": ([vp, vp, vp, vp, i, vp, vp], i),
@@ -199,6 +201,23 @@ def haf_modp(A, primes, kind: int = KIND_HAF):
     check(load().haf_modp_c(ctypes.c_void_p(ptr), n, max(n, 1), kind, ctypes.c_void_p(primes.ctypes.data),
                             len(primes), ctypes.c_void_p(res.ctypes.data)))
     return [int(r) for r in res]
+
+
+def haf_host_dd(A, kind: int = KIND_HAF):
+    """haf / lhaf of a host matrix with every step of each term in double-double
+    (synchronous); returns (re_hi, re_lo, im_hi, im_lo)."""
+    A = _host_matrix(A)
+    n = A.shape[0]
+    ptr = A.ctypes.data if n else ctypes.addressof(ctypes.c_double(0.0))
+    out = c128x2()
+    check(load().haf_dd_c128x2_host(ctypes.c_void_p(ptr), n, max(n, 1), kind, ctypes.byref(out)))
+    return (out.re_hi, out.re_lo, out.im_hi, out.im_lo)
+
+
+def haf_dev_dd(dA_ptr: int, n: int, lda: int, d_out_ptr: int, stream: int = 0, kind: int = KIND_HAF):
+    """Enqueue the double-double mode on a device matrix; d_out receives 4 doubles."""
+    check(load().haf_dd_c128x2_dev(ctypes.c_void_p(dA_ptr), n, lda, kind, ctypes.c_void_p(d_out_ptr),
+                                   ctypes.c_void_p(stream)))
 
 
 def perm_host(W) -> complex:

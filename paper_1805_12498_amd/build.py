@@ -27,6 +27,7 @@ SOURCES = [
     "haf_kernels_series.hip",
     "haf_noalloc.hip",
     "haf_kernels_modp.hip",
+    "haf_kernels_dd.hip",
     "haf_runtime.cpp",
     "haf_batched.cpp",
     "haf_server.cpp",
@@ -49,10 +50,16 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+# sources whose arithmetic must not be contracted into fused multiply-adds
+# (double-double error-free transformations)
+NO_CONTRACT = {"haf_kernels_dd.hip"}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [hipcc()] + HIP_FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-ffp-contract=off"] if src in NO_CONTRACT else []
+    cmd = [hipcc()] + HIP_FLAGS + extra + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

@@ -98,6 +98,16 @@ hipError_t launch_series_group(bool loops, int blocks, hipStream_t st, const Gro
 hipError_t launch_reduce_group(hipStream_t st, const GroupItem* items, int nitems, const double* partials,
                                const int* exps);
 
+// Per-term double-double mode: coefficients of det(I - lambda B) (and loop
+// moments) as complex double-double, hi parts at coef[(k-1) cstride + i] and lo
+// parts at coef[lo_plane + (k-1) cstride + i]; then series and signed
+// double-double block partials (slots slot0 + b).
+hipError_t launch_coef_dd(int s, bool loops, int grid, hipStream_t st, const double2* A, int lda, int N, int m,
+                          uint64_t rank0, int count, const int* d_exp, double2* coef, int64_t cstride,
+                          int64_t lo_plane);
+hipError_t launch_series_dd(bool loops, int count, int N, double sign, hipStream_t st, const double2* coef,
+                            int64_t cstride, int64_t lo_plane, double* partials, int64_t slot0);
+
 // Exponent e of the exact input scaling (off-diagonal by 2^-2e, diagonal by
 // 2^-e; the result is multiplied back by 2^(2eN)), written to *d_exp.
 hipError_t launch_prescale(hipStream_t st, const double2* A, int n, int lda, int* d_exp);

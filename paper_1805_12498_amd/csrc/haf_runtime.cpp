@@ -322,13 +322,46 @@ static int enqueue_haf_multi(int dev, Workspace* w, const Plan& plan, const doub
     return hip_check(launch_reduce(st, w->part, plan.nslots, out_dd, out, d_exp, plan.N), "reduce kernel launch");
 }
 
+constexpr int64_t kChunkDD = 1 << 18;   // subsets per launch of the double-double mode
+
+// The per-term double-double mode: the same plan over size classes (smaller
+// chunks), every coefficient and term in complex double-double, the same
+// partial slots and reduction.
+static int enqueue_haf_dd(int dev, Workspace* w, const double2* dA, int n, int lda, int kind, double* out_dd,
+                          double2* out, hipStream_t st) {
+    const Plan plan = make_plan(n, kind, kChunkDD);
+    const bool loops = kind == HAF_KIND_LHAF;
+    const int64_t lo_plane = plan.max_chunk * plan.ncoef;
+    int rc = workspace_reserve(w, st, (size_t)(2 * lo_plane) * sizeof(double2), (size_t)plan.nslots * 4 * sizeof(double),
+                               64);
+    if (rc) return rc;
+    int* d_exp = (int*)w->aux;
+    if ((rc = hip_check(launch_prescale(st, dA, n, lda, d_exp), "prescale kernel launch"))) return rc;
+    for (const Chunk& c : plan.chunks) {
+        const int pidx = prof_begin(st, 0, (double)c.count * coef_model_flops(2 * c.m, plan.N, loops), c.count);
+        rc = hip_check(launch_coef_dd(2 * c.m, loops, coef_grid(dev, c.count), st, dA, lda, plan.N, c.m, c.rank0,
+                                      c.count, d_exp, w->coef, c.count, lo_plane),
+                       "double-double coefficient kernel launch");
+        prof_end(pidx, st);
+        if (rc) return rc;
+        const double sign = ((plan.N - c.m) & 1) ? -1.0 : 1.0;
+        if ((rc = hip_check(launch_series_dd(loops, c.count, plan.N, sign, st, w->coef, c.count, lo_plane, w->part,
+                                             c.slot0),
+                            "double-double series kernel launch")))
+            return rc;
+    }
+    return hip_check(launch_reduce(st, w->part, plan.nslots, out_dd, out, d_exp, plan.N), "reduce kernel launch");
+}
+
 // Enqueue one hafnian of an n x n device matrix (n even, 2 <= n <= 64).
-int enqueue_haf(const double2* dA, int n, int lda, int kind, double* out_dd, double2* out, hipStream_t st) {
+int enqueue_haf(const double2* dA, int n, int lda, int kind, double* out_dd, double2* out, hipStream_t st,
+                int prec = 0) {
     int dev = 0;
     int rc = ensure_device(&dev);
     if (rc) return rc;
     Workspace* w = nullptr;
     if ((rc = workspace_for(st, &w))) return rc;
+    if (prec == 1) return enqueue_haf_dd(dev, w, dA, n, lda, kind, out_dd, out, st);
     const Plan plan = make_plan(n, kind, kChunk);
     const bool loops = kind == HAF_KIND_LHAF;
     // Small matrices (N <= 16, one chunk per size class) on the default path: all
@@ -357,7 +390,7 @@ int enqueue_haf(const double2* dA, int n, int lda, int kind, double* out_dd, dou
 }
 
 // Device-side entry: handles n = 0, odd n and the padding for odd-n lhaf.
-int run_dev(const double2* dA, int n, int lda, int kind, double* out_dd, double2* out, hipStream_t st) {
+int run_dev(const double2* dA, int n, int lda, int kind, double* out_dd, double2* out, hipStream_t st, int prec) {
     int rc = ensure_device(nullptr);
     if (rc) return rc;
     if (n == 0) return hip_check(launch_write_const(st, 1.0, out_dd, out), "write kernel launch");
@@ -368,9 +401,9 @@ int run_dev(const double2* dA, int n, int lda, int kind, double* out_dd, double2
         const size_t need = (size_t)(n + 1) * (n + 1) * sizeof(double2);
         if ((rc = grow((void**)&w->pad, &w->pad_cap, need, st))) return rc;
         if ((rc = hip_check(launch_pad_odd(st, dA, n, lda, w->pad), "pad kernel launch"))) return rc;
-        return enqueue_haf(w->pad, n + 1, n + 1, kind, out_dd, out, st);
+        return enqueue_haf(w->pad, n + 1, n + 1, kind, out_dd, out, st, prec);
     }
-    return enqueue_haf(dA, n, lda, kind, out_dd, out, st);
+    return enqueue_haf(dA, n, lda, kind, out_dd, out, st, prec);
 }
 
 int check_dims(const void* p, int n, int lda, int kind) {
@@ -411,7 +444,7 @@ static hipStream_t host_stream() {
     return s;
 }
 
-int run_host(const haf_cplx* A, int n, int lda, int kind, haf_cplx2* out) {
+int run_host(const haf_cplx* A, int n, int lda, int kind, haf_cplx2* out, int prec = 0) {
     int rc = check_dims(A, n, lda, kind);
     if (rc) return rc;
     if (!out) return set_error(HAF_E_INVALID_ARG, "null output");
@@ -429,7 +462,7 @@ int run_host(const haf_cplx* A, int n, int lda, int kind, haf_cplx2* out) {
                                                   (size_t)n * sizeof(double2), (size_t)n, hipMemcpyHostToDevice, st),
                                  "matrix upload")))
         return rc;
-    if ((rc = run_dev(dA, n, n, kind, dout, nullptr, st))) return rc;
+    if ((rc = run_dev(dA, n, n, kind, dout, nullptr, st, prec))) return rc;
     double h[4];
     if ((rc = hip_check(hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, st), "result download"))) return rc;
     if ((rc = hip_check(hipStreamSynchronize(st), "stream synchronize"))) return rc;
@@ -579,6 +612,19 @@ int lhaf_c128_dev(const haf_cplx* dA, int n, int lda, haf_cplx* d_out, void* str
 
 int haf_c128x2_dev(const haf_cplx* dA, int n, int lda, int kind, haf_cplx2* d_out, void* stream) {
     return dev_entry(dA, n, lda, kind, (double*)d_out, nullptr, stream);
+}
+
+int haf_dd_c128x2_dev(const haf_cplx* dA, int n, int lda, int kind, haf_cplx2* d_out, void* stream) {
+    clear_error();
+    int rc = check_dims(dA, n, lda, kind);
+    if (rc) return rc;
+    if (!d_out) return set_error(HAF_E_INVALID_ARG, "null output");
+    return run_dev((const double2*)dA, n, lda, kind, (double*)d_out, nullptr, (hipStream_t)stream, 1);
+}
+
+int haf_dd_c128x2_host(const haf_cplx* A, int n, int lda, int kind, haf_cplx2* out) {
+    clear_error();
+    return run_host(A, n, lda, kind, out, 1);
 }
 
 int perm_c128(const haf_cplx* W, int n, int ldw, haf_cplx* out) {

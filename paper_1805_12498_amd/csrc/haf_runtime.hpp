@@ -51,7 +51,8 @@ int check_values(const haf_cplx* A, int n, int lda);
 int launch_coef_chunk(int dev, const double2* dA, int lda, int N, int m, uint64_t rank0, int count,
                       const uint32_t* masks, bool loops, const int* d_exp, double2* coef, int64_t cstride,
                       hipStream_t st);
-int run_dev(const double2* dA, int n, int lda, int kind, double* out_dd, double2* out, hipStream_t st);
+int run_dev(const double2* dA, int n, int lda, int kind, double* out_dd, double2* out, hipStream_t st,
+            int prec = 0);   // prec 1: every step of each term in double-double
 double now_seconds();
 int grow(void** p, size_t* cap, size_t need, hipStream_t st);   // (re)allocate device memory, 1.25x headroom
 int hip_check(hipError_t e, const char* what);
