@@ -59,9 +59,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(A, n, loops, seconds_target=15.0):
-    """The CPU oracle (long double, explicit-power route) on a uniform random
-    sample of subsets of the same matrix, scaled to subset-terms/s."""
+    """The CPU oracle's formula route (explicit matrix powers) instantiated on double,
+    on a uniform random sample of subsets of the same matrix, scaled to subset-terms/s."""
     import numpy as np
 
     import oracle
@@ -70,16 +81,116 @@ def cpu_baseline(A, n, loops, seconds_target=15.0):
     rng = np.random.default_rng(12345)
     probe = rng.integers(1, 1 << N, size=64 * threads, dtype=np.int64).astype(np.uint32)
     t0 = time.time()
-    oracle.formula_masks(A, probe, loops=loops, prec="ld", threads=threads)
+    oracle.formula_masks(A, probe, loops=loops, prec="d", threads=threads)
     dt = max(time.time() - t0, 1e-3)
-    count = int(max(64 * threads, min(4_000_000, len(probe) * seconds_target / dt)))
+    count = int(max(64 * threads, min(20_000_000, len(probe) * seconds_target / dt)))
     masks = rng.integers(1, 1 << N, size=count, dtype=np.int64).astype(np.uint32)
     t0 = time.time()
-    oracle.formula_masks(A, masks, loops=loops, prec="ld", threads=threads)
+    oracle.formula_masks(A, masks, loops=loops, prec="d", threads=threads)
     dt = time.time() - t0
     return {"value": count / dt, "unit": "subset-terms/s", "cores": threads, "kind": "oracle",
-            "sample": "%d uniformly random subsets of the %dx%d matrix (%s), long double, %.1f s" % (
-                count, n, n, "lhaf" if loops else "haf", dt)}
+            "cpu": cpu_model(),
+            "sample": "%d uniformly random subsets of the %dx%d matrix (%s), the oracle's formula route "
+                      "(explicit matrix powers) in double, %.1f s on %d threads" % (
+                          count, n, n, "lhaf" if loops else "haf", dt, threads)}
+
+
+def gold_values():
+    path = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
+    return json.load(open(path)) if os.path.exists(path) else {}
+
+
+def gold_hp(g, name):
+    import oracle
+    v = g[name]["value"]
+    return oracle.HighPrec((v["re"][0], v["re"][1], v["im"][0], v["im"][1]))
+
+
+def bench_configs(hg, gi):
+    """Timing and relative error of every configuration besides the headline one."""
+    import numpy as np
+    import torch
+
+    g = gold_values()
+    st = torch.cuda.current_stream()
+    out = {}
+    dout = torch.zeros(4, dtype=torch.float64, device="cuda")
+
+    def timed(fn, reps):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return np.array(ts)
+
+    def result():
+        r = dout.cpu().numpy()
+        return complex(r[0] + r[1], r[2] + r[3])
+
+    # C1: one 16x16 hafnian per call, latency distribution of the plain path
+    A = gi.gaussian_symmetric(16, gi.SEED_N16)
+    dA = torch.from_numpy(A).cuda()
+    fn = lambda: hg.haf_dev(dA.data_ptr(), 16, 16, dout.data_ptr(), st.cuda_stream, kind=0, x2=True)  # noqa: E731
+    timed(fn, 20)
+    ts = timed(fn, 1000)
+    c1 = {"workload": "haf of the 16x16 Gaussian matrix, seed 1601, 2^8 subsets, one call at a time",
+          "p10_ms": float(np.percentile(ts, 10) * 1e3), "p50_ms": float(np.median(ts) * 1e3),
+          "p90_ms": float(np.percentile(ts, 90) * 1e3), "calls": len(ts)}
+    if "n16_haf" in g:
+        c1["relerr"] = gold_hp(g, "n16_haf").relerr(result())
+        c1["relerr_vs"] = "oracle formula route in binary128"
+    out["C1_n16_haf"] = c1
+    log("C1:", c1)
+
+    # C2: 40x40, haf and lhaf, double and per-term double-double
+    A = gi.gaussian_symmetric(40, gi.SEED_N40)
+    dA = torch.from_numpy(A).cuda()
+    for kind, name in ((0, "haf"), (1, "lhaf")):
+        fn = lambda: hg.haf_dev(dA.data_ptr(), 40, 40, dout.data_ptr(), st.cuda_stream, kind=kind, x2=True)  # noqa: E731
+        timed(fn, 2)
+        ts = timed(fn, 30)
+        c2 = {"workload": "%s of the 40x40 Gaussian matrix, seed 4001, 2^20 subsets" % name,
+              "ms_median": float(np.median(ts) * 1e3), "subset_terms_per_s": (1 << 20) / float(np.median(ts))}
+        key = "n40_" + name
+        if key in g:
+            c2["relerr"] = gold_hp(g, key).relerr(result())
+            c2["kappa"] = g[key]["kappa"]
+            c2["relerr_vs"] = "oracle formula route in double-double"
+        fdd = lambda: hg.haf_dev_dd(dA.data_ptr(), 40, 40, dout.data_ptr(), st.cuda_stream, kind=kind)  # noqa: E731
+        ts = timed(fdd, 3)
+        c2["dd_mode_ms_median"] = float(np.median(ts) * 1e3)
+        if key in g:
+            import oracle
+            r = dout.cpu().numpy()
+            c2["dd_mode_relerr"] = gold_hp(g, key).relerr_hp(oracle.HighPrec(tuple(float(x) for x in r)))
+        out["C2_n40_" + name] = c2
+        log("C2 %s:" % name, c2)
+
+    # C3b: the 56-vertex 0/1 graph, double path and the exact modular path
+    G = gi.random_graph(56, 0.5, gi.SEED_N56_GRAPH)
+    dA = torch.from_numpy(G.astype(np.complex128)).cuda()
+    fn = lambda: hg.haf_dev(dA.data_ptr(), 56, 56, dout.data_ptr(), st.cuda_stream, kind=0, x2=True)  # noqa: E731
+    ts = timed(fn, 1)
+    c3b = {"workload": "haf of the 56-vertex 0/1 graph G(56, 1/2), seed 5602, 2^28 subsets",
+           "ms": float(ts[0] * 1e3), "subset_terms_per_s": (1 << 28) / float(ts[0])}
+    got = result()
+    t0 = time.perf_counter()
+    exact = hg.haf_exact(G, 0)
+    c3b["exact_path_s"] = time.perf_counter() - t0
+    c3b["exact_path_value"] = str(exact)
+    if "n56_graph_exact" in g:
+        ref = int(g["n56_graph_exact"]["exact"])
+        c3b["exact_path_equals_oracle"] = exact == ref
+        c3b["relerr"] = abs(complex(got) - ref) / ref
+        c3b["relerr_vs"] = "the oracle's exact count (sum over F_p for six 31-bit primes, CRT)"
+    else:
+        c3b["relerr_vs_exact_path"] = abs(complex(got) - exact) / abs(exact)
+    out["C3b_n56_graph"] = c3b
+    log("C3b:", c3b)
+    return out
 
 
 def bench_batched(hg, gi, count=4096):
@@ -183,6 +294,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--kernel-path", type=int, default=0)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     args = ap.parse_args()
@@ -264,6 +376,8 @@ def main():
         "fp64_model_tflops_step": prof["coef_model_flops"] / secs / 1e12,
         "cpu_baseline": None,
     }
+    if not args.no_configs:
+        line["configs"] = bench_configs(hg, gi)
     if not args.no_batched:
         line["batched"] = bench_batched(hg, gi)
     if not args.no_serving:

@@ -36,7 +36,7 @@ def tolerance(W):
     if W.shape[0] == 0:
         return 0.0
     _, kappa = oracle.formula(embed(W), False, prec="dd", want_kappa=True)
-    return max(1e-12, 64 * EPS * kappa)
+    return 64 * EPS * kappa
 
 
 def rand_c(n, seed, scale=0.7):

@@ -191,6 +191,43 @@ def test_single_term_complete_graph(n):
         assert abs(got - float(want)) <= 1e-25 * max(1.0, abs(float(want))) * 1e10
 
 
+@pytest.mark.parametrize("n", [8, 12, 16])
+def test_kappa_complete_graph_closed_form(n):
+    """kappa = sum_Z |f(Z)| / |haf| for A = J - I from the closed-form single terms above:
+    f(Z) depends only on m = |Z|, so sum_Z |f(Z)| = sum_m C(N, m) |f_m| and haf = (n-1)!!.
+    Every parity tolerance scales with the oracle's kappa, so an over-estimate would
+    loosen every GPU test; this pins it."""
+    N = n // 2
+    J = gi.complete_graph(n).astype(complex)
+    total = Fraction(0)
+    for m in range(1, N + 1):
+        fm = _series_coeff([(2 * m - 1, Fraction(1, 2)), (-1, Fraction(m - 1, 2)), (1, Fraction(m, 2))], N)
+        total += math.comb(N, m) * abs(fm)
+    want = float(total / cf.haf_complete(n))
+    for prec in ("d", "ld", "dd", "q"):
+        r, kappa = oracle.formula(J, prec=prec, want_kappa=True)
+        assert abs(kappa - want) <= 1e-12 * want, (prec, kappa, want)
+
+
+@pytest.mark.parametrize("n", [6, 10, 14])
+def test_formula_masks_against_closed_forms_and_brute_force(n):
+    """formula_masks: one mask of J - I gives (-1)^(N-m) f_m (the closed-form term with
+    the sign of Eq. Pset); all nonzero masks of a random matrix give the brute-force haf."""
+    N = n // 2
+    J = gi.complete_graph(n).astype(complex)
+    for mask in (1, (1 << N) - 1, 0b101 & ((1 << N) - 1) or 1):
+        m = bin(mask).count("1")
+        fm = _series_coeff([(2 * m - 1, Fraction(1, 2)), (-1, Fraction(m - 1, 2)), (1, Fraction(m, 2))], N)
+        want = float(fm) * (-1) ** (N - m)
+        got = oracle.formula_masks(J, np.array([mask], dtype=np.uint32), prec="q").value
+        assert abs(got - want) <= 1e-25 * max(1.0, abs(want)) * 1e10
+    A = rand_sym(n, 500 + n)
+    masks = np.arange(1, 1 << N, dtype=np.uint32)
+    for loops in (False, True):
+        got = oracle.formula_masks(A, masks, loops=loops, prec="dd").value
+        assert rel(got, oracle.brute(A, loops).value) < 1e-13
+
+
 @pytest.mark.parametrize("n", [8, 14])
 def test_single_term_complete_graph_loops(n):
     """A = J (unit loops): l_k = s (2m-1)^(k-1), so the loop factor is exp(sum_{k<=N} m (2m-1)^(k-1) l^k)."""
