@@ -282,25 +282,36 @@ int haf_profile_read(haf_profile* out);
  * submit() validates the matrix (as the host entry points do), copies it and
  * queues it; it never waits for the device.  The server's scheduler thread
  * admits queued requests in arrival order whenever a request slot is free and
- * the device arena holds room for the request's state (its matrix and its
- * result), and enqueues each admitted request at once on the least-loaded of
- * its streams, so that requests admitted while others run overlap with them
- * on the device.  A result is bitwise the single-matrix path's result for that
- * matrix, whatever else the server runs.  Results are collected with poll().
- * The per-stream work buffers of the hafnian computation are the library's
- * usual workspaces and are not counted in arena_bytes.                       */
+ * the device arena holds the request's whole device state: its matrix, the
+ * padded copy of an odd-n loop hafnian, the exponent of its input scaling and
+ * its partial slots (32 bytes per 256 subsets).  The other device memory of a
+ * server (the tick coefficient buffer of tick_coef_bytes and small tick tables)
+ * is allocated once at start.  Work runs in ticks on one stream: a tick takes
+ * runs of subsets of one size class (cut at 256-subset boundaries) from every
+ * admitted request, round-robin in admission order, up to tick_flops model
+ * flops (44/3 s^3 per subset of s rows, + 8 (N-1) s^2 for loop hafnians) and
+ * tick_coef_bytes of coefficients, and launches them together: one prologue for
+ * the requests that start, one coefficient launch per register layout and kind,
+ * one series launch per kind, one reduction for the requests that finish.  Two
+ * ticks are enqueued ahead, so requests that arrive while a tick runs join the
+ * next one, small requests finish within a tick or two of admission, and large
+ * ones proceed a share of the budget per tick.  A result is bitwise the
+ * single-matrix path's result for that matrix, whatever else the server runs.
+ * Results are collected with poll().  With continuous = 0 the server runs one
+ * request at a time through the single-matrix path (the plain server; its
+ * single-matrix workspaces come on top of the arena).                        */
 typedef struct haf_server haf_server;
 
 typedef struct {
     int device;                 /* HIP device ordinal                                  */
-    int64_t arena_bytes;        /* device bytes for admitted requests: n^2 * 16 rounded
-                                   up to 256, plus 256, per request                     */
-    int max_active;             /* request slots on the device                          */
+    int64_t arena_bytes;        /* device bytes for the state of admitted requests     */
+    int max_active;             /* request slots                                       */
     int max_queue;              /* host queue length before submit returns HAF_E_BUSY   */
-    int streams;                /* streams the admitted requests are spread over        */
-    int continuous;             /* 1: admit whenever there is room (continuous batching);
-                                   0: one request at a time on one stream, in arrival
-                                   order (the plain server)                             */
+    double tick_flops;          /* model flops of the work one tick launches (> 0)     */
+    int64_t tick_coef_bytes;    /* coefficient memory of one tick (>= 512 KiB)          */
+    int continuous;             /* 1: ticks over every admitted request (continuous
+                                   batching); 0: one request at a time through the
+                                   single-matrix path, in arrival order (plain)         */
 } haf_server_config;
 
 typedef struct {
@@ -312,7 +323,8 @@ typedef struct {
     double t_submit, t_admit, t_done;   /* seconds on the host steady clock (haf_now) */
 } haf_result;
 
-/* Fill *cfg with defaults (1 GiB arena, 256 slots, 8 streams, continuous). */
+/* Fill *cfg with defaults (1 GiB arena, 256 slots, 2e10 flops and 256 MiB of
+ * coefficients per tick, continuous). */
 void haf_server_default_config(haf_server_config* cfg);
 /* Start a server: allocates the arena and starts its scheduler thread.  NULL
  * on failure (haf_last_error() says why). */

@@ -50,7 +50,8 @@ class c128x2(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("arena_bytes", ctypes.c_int64), ("max_active", ctypes.c_int),
-                ("max_queue", ctypes.c_int), ("streams", ctypes.c_int), ("continuous", ctypes.c_int)]
+                ("max_queue", ctypes.c_int), ("tick_flops", ctypes.c_double), ("tick_coef_bytes", ctypes.c_int64),
+                ("continuous", ctypes.c_int)]
 
 
 class Profile(ctypes.Structure):

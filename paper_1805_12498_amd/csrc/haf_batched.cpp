@@ -306,6 +306,7 @@ static int run_grouped(const double2* dA, const int64_t* offs, const int32_t* ns
         it.lda = it.src_lda;
         it.cval = gp.cval[(size_t)j];
         it.pad_ = 0;
+        it.exp = w->dstate + j;
         if (it.cval == kGroupComputed && it.n != ns[t]) {   // odd-n loop hafnian: dense padded copy
             it.A = w->pad + pad_off;
             it.lda = it.n;
@@ -324,23 +325,22 @@ static int run_grouped(const double2* dA, const int64_t* offs, const int32_t* ns
     w->staged_used = true;
     const GroupItem* ditems = (const GroupItem*)w->dmeta;
     const GroupChunk* dch = (const GroupChunk*)(w->dmeta + items_b);
-    int* exps = w->dstate;
 
-    if ((rc = hip_check(launch_group_prologue(st, ditems, ni, exps), "batch prologue launch"))) return rc;
+    if ((rc = hip_check(launch_group_prologue(st, ditems, ni), "batch prologue launch"))) return rc;
     for (const StageLaunch& L : gp.launches) {
         hipError_t e;
         if (L.what == 0) {
             int64_t subsets = 0;
             for (int c = 0; c < L.nch; ++c) subsets += gp.chunks[L.first + (size_t)c].count;
             const int pidx = prof_begin(st, 2, L.flops, subsets);
-            e = launch_coef_reg_group(L.layout, L.loops, L.blocks, st, ditems, dch + L.first, L.nch, exps, w->coef);
+            e = launch_coef_reg_group(L.layout, L.loops, L.blocks, st, ditems, dch + L.first, L.nch, w->coef);
             prof_end(pidx, st);
         } else {
-            e = launch_series_group(L.loops, L.blocks, st, dch + L.first, L.nch, w->coef, w->part);
+            e = launch_series_group(L.loops, 16, L.blocks, st, dch + L.first, L.nch, w->coef, w->part);
         }
         if ((rc = hip_check(e, "batch kernel launch"))) return rc;
     }
-    return hip_check(launch_reduce_group(st, ditems, ni, w->part, exps), "batch reduce launch");
+    return hip_check(launch_reduce_group(st, ditems, ni, w->part), "batch reduce launch");
 }
 
 // ------------------------------------------------------------------ stream pool

@@ -60,7 +60,7 @@ HAF_REG_TABLE(HAF_INST_REG_MULTI)
 template <int P, int Q, int R, int C, int CP, bool LOOPS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 ? 2 : 1))) void k_coef_reg_group(
     const GroupItem* __restrict__ items, const GroupChunk* __restrict__ chunks, int nchunks,
-    const int* __restrict__ exps, double2* __restrict__ coef) {
+    double2* __restrict__ coef) {
     using S = RegShape<P, Q, R, C>;
     __shared__ double2 lds[S::W * S::PER];
     const int blk = (int)blockIdx.x;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 
     const int groups = (gend - ch.gstart) * S::W;
     const int span = (ch.count + groups - 1) / groups;
     const GroupItem it = items[ch.item];
-    const int e = exps[ch.item];
+    const int e = *it.exp;
     coef_reg_span<P, Q, R, C, CP, LOOPS>(lds, it.A, it.lda, ch.N, ch.m, ch.rank0, ch.count, nullptr,
                                          ldexp(1.0, -2 * e), ldexp(1.0, -e), coef + ch.coff, ch.count,
                                          (blk - ch.gstart) * S::W, span, threadIdx.x);
@@ -83,9 +83,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 
 
 #define HAF_INST_REG_GROUP(P, Q, R, C, CP, LO, HI)                                                          \
     template __global__ void k_coef_reg_group<P, Q, R, C, CP, false>(const GroupItem*, const GroupChunk*,   \
-                                                                     int, const int*, double2*);            \
+                                                                     int, double2*);                        \
     template __global__ void k_coef_reg_group<P, Q, R, C, CP, true>(const GroupItem*, const GroupChunk*,    \
-                                                                    int, const int*, double2*);
+                                                                    int, double2*);
 HAF_REG_TABLE(HAF_INST_REG_GROUP)
 
 int reg_layout_count() {
@@ -120,15 +120,15 @@ int group_coef_blocks(int layout, int count, int span) {
 }
 
 hipError_t launch_coef_reg_group(int layout, bool loops, int blocks, hipStream_t st, const GroupItem* items,
-                                 const GroupChunk* chunks, int nchunks, const int* exps, double2* coef) {
+                                 const GroupChunk* chunks, int nchunks, double2* coef) {
     if (nchunks < 1 || blocks < 1) return hipErrorInvalidValue;
     int i = 0;
 #define HAF_TRY_GROUP(P, Q, R, C, CP, LO, HI)                                                                 \
     if (i++ == layout) {                                                                                      \
         if (loops) hipLaunchKernelGGL((k_coef_reg_group<P, Q, R, C, CP, true>), dim3(blocks), dim3(64), 0, st, \
-                                      items, chunks, nchunks, exps, coef);                                    \
+                                      items, chunks, nchunks, coef);                                          \
         else hipLaunchKernelGGL((k_coef_reg_group<P, Q, R, C, CP, false>), dim3(blocks), dim3(64), 0, st,     \
-                                items, chunks, nchunks, exps, coef);                                          \
+                                items, chunks, nchunks, coef);                                                \
         return hipGetLastError();                                                                             \
     }
     HAF_REG_TABLE(HAF_TRY_GROUP)

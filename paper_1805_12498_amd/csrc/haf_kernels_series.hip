@@ -62,11 +62,11 @@ __global__ __launch_bounds__(kSeriesBlock) void k_series(const double2* __restri
     block_partial(sign, f, partials + 4 * (slot0 + blockIdx.x));
 }
 
-// Matrices of a batch (every N <= 16): the workgroup finds its chunk by a
+// Matrices of a batch (every N <= NMAX): the workgroup finds its chunk by a
 // binary search over the launch's chunk table, then as k_series with the
 // chunk's own N (the series body gives bitwise the same term for a given N
 // whatever its compile-time bound).
-template <bool LOOPS>
+template <int NMAX, bool LOOPS>
 __global__ __launch_bounds__(kSeriesBlock) void k_series_group(const GroupChunk* __restrict__ chunks, int nchunks,
                                                                const double2* __restrict__ coef,
                                                                double* __restrict__ partials) {
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kSeriesBlock) void k_series_group(const GroupChunk*
     const int lb = blk - ch.gstart;
     const int t = lb * kSeriesBlock + threadIdx.x;
     double2 f = cz();
-    if (t < ch.count) f = subset_series_upto<16, LOOPS>(coef + ch.coff, ch.count, t, ch.N);
+    if (t < ch.count) f = subset_series_upto<NMAX, LOOPS>(coef + ch.coff, ch.count, t, ch.N);
     block_partial(ch.sign, f, partials + 4 * (ch.slot + lb));
 }
 
@@ -125,15 +125,12 @@ static const SeriesMultiFn g_series_multi[17][2] = {
 
 int group_series_blocks(int count) { return (count + kSeriesBlock - 1) / kSeriesBlock; }
 
-hipError_t launch_series_group(bool loops, int blocks, hipStream_t st, const GroupChunk* chunks, int nchunks,
-                               const double2* coef, double* partials) {
-    if (nchunks < 1 || blocks < 1) return hipErrorInvalidValue;
-    if (loops)
-        hipLaunchKernelGGL(k_series_group<true>, dim3(blocks), dim3(kSeriesBlock), 0, st, chunks, nchunks, coef,
-                           partials);
-    else
-        hipLaunchKernelGGL(k_series_group<false>, dim3(blocks), dim3(kSeriesBlock), 0, st, chunks, nchunks, coef,
-                           partials);
+hipError_t launch_series_group(bool loops, int nmax, int blocks, hipStream_t st, const GroupChunk* chunks,
+                               int nchunks, const double2* coef, double* partials) {
+    if (nchunks < 1 || blocks < 1 || nmax < 1 || nmax > 32) return hipErrorInvalidValue;
+    auto k = nmax <= 16 ? (loops ? k_series_group<16, true> : k_series_group<16, false>)
+                        : (loops ? k_series_group<32, true> : k_series_group<32, false>);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(kSeriesBlock), 0, st, chunks, nchunks, coef, partials);
     return hipGetLastError();
 }
 
@@ -193,11 +190,10 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
 
 // One workgroup per matrix of a batch (the single-matrix reduction).
 __global__ __launch_bounds__(256) void k_reduce_group(const GroupItem* __restrict__ items,
-                                                       const double* __restrict__ partials,
-                                                       const int* __restrict__ exps) {
+                                                       const double* __restrict__ partials) {
     const GroupItem it = items[blockIdx.x];
     if (it.cval != kGroupComputed) return;    // written by the prologue
-    reduce_partials_block(partials + 4 * it.slot_base, it.nslots, it.out_dd, it.out, exps[blockIdx.x], it.n / 2);
+    reduce_partials_block(partials + 4 * it.slot_base, it.nslots, it.out_dd, it.out, *it.exp, it.n / 2);
 }
 
 // Exponent of the exact input scaling.  With f the largest |Re|, |Im| of an
@@ -237,14 +233,14 @@ __global__ __launch_bounds__(256) void k_prescale(const double2* __restrict__ A,
 // weight 1, as the pad kernel builds it) and the exponent from the caller's
 // matrix (padding adds only zeros off the diagonal, so the exponent is that of
 // the padded matrix).
-__global__ __launch_bounds__(256) void k_group_prologue(const GroupItem* __restrict__ items, int* __restrict__ exps) {
+__global__ __launch_bounds__(256) void k_group_prologue(const GroupItem* __restrict__ items) {
     const GroupItem it = items[blockIdx.x];
     if (it.cval != kGroupComputed) {
         if (threadIdx.x == 0) {
             const double v = it.cval == kGroupConstOne ? 1.0 : 0.0;
             if (it.out) *it.out = make_double2(v, 0.0);
             if (it.out_dd) { it.out_dd[0] = v; it.out_dd[1] = 0.0; it.out_dd[2] = 0.0; it.out_dd[3] = 0.0; }
-            exps[blockIdx.x] = 0;
+            *it.exp = 0;
         }
         return;
     }
@@ -259,7 +255,7 @@ __global__ __launch_bounds__(256) void k_group_prologue(const GroupItem* __restr
         }
     }
     const int e = prescale_exp_block(it.src, it.src_n, it.src_lda);
-    if (threadIdx.x == 0) exps[blockIdx.x] = e;
+    if (threadIdx.x == 0) *it.exp = e;
 }
 
 __global__ void k_scatter(const double2* __restrict__ in, const int* __restrict__ perm, int count,
@@ -352,16 +348,15 @@ hipError_t launch_write_const(hipStream_t st, double re, double* out_dd, double2
     return hipGetLastError();
 }
 
-hipError_t launch_group_prologue(hipStream_t st, const GroupItem* items, int nitems, int* exps) {
+hipError_t launch_group_prologue(hipStream_t st, const GroupItem* items, int nitems) {
     if (nitems < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_group_prologue, dim3(nitems), dim3(256), 0, st, items, exps);
+    hipLaunchKernelGGL(k_group_prologue, dim3(nitems), dim3(256), 0, st, items);
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_group(hipStream_t st, const GroupItem* items, int nitems, const double* partials,
-                               const int* exps) {
+hipError_t launch_reduce_group(hipStream_t st, const GroupItem* items, int nitems, const double* partials) {
     if (nitems < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_group, dim3(nitems), dim3(256), 0, st, items, partials, exps);
+    hipLaunchKernelGGL(k_reduce_group, dim3(nitems), dim3(256), 0, st, items, partials);
     return hipGetLastError();
 }
 

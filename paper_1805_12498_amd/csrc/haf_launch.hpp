@@ -66,6 +66,7 @@ struct GroupItem {
     double* out_dd;                      // double-double result (re_hi, re_lo, im_hi, im_lo), or null
     int n, lda, src_n, src_lda;
     int cval, pad_;                      // kGroupComputed, or the constant result the prologue writes
+    int* exp;                            // exponent of the matrix's exact input scaling (the prologue writes it)
     int64_t slot_base;                   // the matrix's first partial slot
     int64_t nslots;                      // its partial slots
 };
@@ -77,9 +78,9 @@ struct GroupChunk {
     double sign;                         // (-1)^(N - m)
 };
 // One workgroup per matrix: write constant results, pad odd-n loop hafnians
-// into A, exponent of the exact input scaling into exps[j] (as the prescale
+// into A, exponent of the exact input scaling into *exp (as the prescale
 // kernel computes it).
-hipError_t launch_group_prologue(hipStream_t st, const GroupItem* items, int nitems, int* exps);
+hipError_t launch_group_prologue(hipStream_t st, const GroupItem* items, int nitems);
 // Coefficients of the chunks of one launch, all served by register layout
 // `layout` (an index into the layout table; every chunk's s = 2m must lie in
 // the layout's range (SM - 8, SM]); blocks = the launch's grid, as planned by
@@ -89,14 +90,13 @@ int reg_layout_sm(int layout);           // largest s of the layout
 int reg_layout_groups(int layout);       // matrices per wave
 int group_coef_blocks(int layout, int count, int span);
 hipError_t launch_coef_reg_group(int layout, bool loops, int blocks, hipStream_t st, const GroupItem* items,
-                                 const GroupChunk* chunks, int nchunks, const int* exps, double2* coef);
-// Series + signed block partials of the chunks of one launch (every N <= 16).
+                                 const GroupChunk* chunks, int nchunks, double2* coef);
+// Series + signed block partials of the chunks of one launch (every N <= nmax <= 32).
 int group_series_blocks(int count);
-hipError_t launch_series_group(bool loops, int blocks, hipStream_t st, const GroupChunk* chunks, int nchunks,
-                               const double2* coef, double* partials);
+hipError_t launch_series_group(bool loops, int nmax, int blocks, hipStream_t st, const GroupChunk* chunks,
+                               int nchunks, const double2* coef, double* partials);
 // One workgroup per matrix: its partials reduced as the single-matrix path does.
-hipError_t launch_reduce_group(hipStream_t st, const GroupItem* items, int nitems, const double* partials,
-                               const int* exps);
+hipError_t launch_reduce_group(hipStream_t st, const GroupItem* items, int nitems, const double* partials);
 
 // Per-term double-double mode: coefficients of det(I - lambda B) (and loop
 // moments) as complex double-double, hi parts at coef[(k-1) cstride + i] and lo

@@ -199,6 +199,26 @@ int release_workspaces() {
     return HAF_OK;
 }
 
+void release_stream_workspace(hipStream_t st) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    DeviceState* ds = device_state(dev);
+    if (!ds) return;
+    std::lock_guard<std::mutex> lk(ds->mu);
+    auto it = ds->ws.find(st);
+    if (it == ds->ws.end()) return;
+    (void)hipStreamSynchronize(st);
+    Workspace* w = it->second;
+    if (w->coef) (void)hipFree(w->coef);
+    if (w->part) (void)hipFree(w->part);
+    if (w->aux) (void)hipFree(w->aux);
+    if (w->pad) (void)hipFree(w->pad);
+    if (w->in) (void)hipFree(w->in);
+    if (w->emb) (void)hipFree(w->emb);
+    delete w;
+    ds->ws.erase(it);
+}
+
 int hip_check(hipError_t e, const char* what) {
     if (e == hipSuccess) return HAF_OK;
     return set_error(HAF_E_DEVICE, "%s: %s", what, hipGetErrorString(e));

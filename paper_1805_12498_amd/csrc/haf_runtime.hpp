@@ -60,6 +60,7 @@ int prof_begin(hipStream_t st, int what, double flops, int64_t subsets);
 void prof_end(int idx, hipStream_t st);
 double coef_model_flops(int s, int N, bool loops);
 void release_batch_workspaces();
+void release_stream_workspace(hipStream_t st);   // free the workspace kept for one stream (current device)
 int noalloc_setup(int dev);   // device address of the allocation-free entry point's scratch array
 
 }  // namespace hafgpu

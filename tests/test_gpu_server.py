@@ -1,9 +1,13 @@
 """GPU tests of the continuous-batching request server through the C ABI.
 
 Every result must be bitwise the single-matrix path's result for the same
-matrix (alone versus in the mix), match the oracle, carry ordered timestamps,
-and the server must finish every request whatever its arena and slot limits.
+matrix (alone versus in the mix, whatever the tick budget), match the oracle,
+carry ordered timestamps, and the server must finish every request whatever its
+arena and slot limits; small requests submitted behind a large one finish
+before it.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -54,7 +58,7 @@ def test_results_alone_vs_mix_and_oracle(hg):
 
 def test_plain_and_continuous_agree(hg):
     trace = gi.serving_trace(60, qps=1e4, seed=11, nmax=28)
-    t1, r1 = serve(hg, trace, continuous=1, streams=8)
+    t1, r1 = serve(hg, trace, continuous=1)
     t0, r0 = serve(hg, trace, continuous=0)
     v1 = {t1[r.ticket][1].tobytes(): complex(r.value.re, r.value.im) for r in r1}
     v0 = {t0[r.ticket][1].tobytes(): complex(r.value.re, r.value.im) for r in r0}
@@ -67,12 +71,22 @@ def test_plain_and_continuous_agree(hg):
         assert a_next >= d_prev - 1e-3
 
 
+def request_bytes(n, kind):
+    """Device state of an admitted request: matrix, padded copy (odd-n lhaf), exponent,
+    partial slots (32 bytes per 256-subset series block of each size class)."""
+    al = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    ne = n + 1 if (n % 2 and kind == 1) else n
+    N = ne // 2
+    slots = sum(-(-math.comb(N, m) // 256) for m in range(1, N + 1))
+    return al(n * n * 16) + (al(ne * ne * 16) if ne != n else 0) + 256 + al(slots * 32)
+
+
 def test_small_arena_and_slots(hg):
-    """An arena that holds two requests at a time and three slots: everything still finishes."""
+    """An arena that holds two of the largest requests at a time and three slots:
+    everything still finishes."""
     trace = gi.serving_trace(30, qps=1e4, seed=12, nmax=30)
-    nmax = max(A.shape[0] for _, _, A in trace)
-    arena = 2 * (((nmax * nmax * 16 + 255) // 256) * 256 + 256)
-    tickets, res = serve(hg, trace, arena_bytes=arena, max_active=3, streams=2)
+    arena = 2 * max(request_bytes(A.shape[0], k) for _, k, A in trace)
+    tickets, res = serve(hg, trace, arena_bytes=arena, max_active=3)
     for r in res:
         kind, A = tickets[r.ticket]
         assert r.status == 0
@@ -118,9 +132,44 @@ def test_submit_errors(hg):
             small.close()
 
 
+def test_tiny_ticks_bitwise(hg):
+    """A tick budget far below one request's work: every request spreads over many ticks
+    (pieces of 256 subsets) and its result is still bitwise the single-matrix result."""
+    trace = gi.serving_trace(16, qps=1e4, seed=14, nmax=36)
+    tickets, res = serve(hg, trace, tick_flops=1e6, tick_coef_bytes=1 << 20)
+    for r in res:
+        kind, A = tickets[r.ticket]
+        assert r.status == 0
+        assert complex(r.value.re, r.value.im) == hg.haf_host(A, kind), (A.shape[0], kind)
+
+
+def test_small_requests_pass_a_large_one(hg):
+    """A 44x44 loop hafnian (2^22 subsets) submitted first, then 20 small requests: the
+    small ones share the ticks with it and finish before it; every result bitwise."""
+    B = gi.serving_trace(1, qps=1e4, seed=15, nmin=44, nmax=44)
+    small = gi.serving_trace(20, qps=1e4, seed=16, nmin=12, nmax=16)
+    trace = [(0.0, 1, B[0][2])] + small
+    srv = hg.Server()
+    try:
+        tickets = {}
+        for _, kind, A in trace:
+            tickets[srv.submit(A, kind)] = (kind, A)
+        srv.drain()
+        res = srv.poll(64)
+    finally:
+        srv.close()
+    big = [r for r in res if tickets[r.ticket][1].shape[0] == 44]
+    rest = [r for r in res if tickets[r.ticket][1].shape[0] != 44]
+    assert len(big) == 1 and len(rest) == 20
+    assert max(r.t_done for r in rest) < big[0].t_done
+    for r in res:
+        kind, A = tickets[r.ticket]
+        assert complex(r.value.re, r.value.im) == hg.haf_host(A, kind), (A.shape[0], kind)
+
+
 def test_destroy_with_pending_requests(hg):
     """Closing a server that still has queued work returns (queued requests are dropped)."""
-    srv = hg.Server(max_active=1, streams=1)
+    srv = hg.Server(max_active=1)
     for _, kind, A in gi.serving_trace(40, qps=1e4, seed=13, nmax=30):
         srv.submit(A, kind)
     srv.close()
