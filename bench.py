@@ -264,23 +264,25 @@ def replay(hg, trace, t_offset, **cfg):
             "seconds": span}
 
 
-def bench_serving(hg, gi, seconds):
-    """Capacity of the plain server (closed loop), then an open-loop Poisson stream at half of it,
-    replayed through both servers."""
-    probe = gi.serving_trace(400, qps=1e9, seed=gi.SEED_SERVE + 1)
+def bench_serving(hg, gi, min_requests=10000):
+    """Capacities of the plain and the continuous server (closed loop), then two open-loop
+    Poisson streams replayed through both: Q1 = half the plain server's capacity (both
+    stable) and Q2 = 0.8 of the continuous server's capacity (the plain server saturates)."""
+    probe = gi.serving_trace(600, qps=1e9, seed=gi.SEED_SERVE + 1)
     plain_cap = replay(hg, probe, 0.0, continuous=0)["haf_per_s"]
     cont_cap = replay(hg, probe, 0.0, continuous=1)["haf_per_s"]
-    qps = 0.5 * plain_cap
-    num = max(200, int(qps * seconds))
-    trace = gi.serving_trace(num, qps=qps, seed=gi.SEED_SERVE)
-    cont = replay(hg, trace, 0.05, continuous=1)
-    plain = replay(hg, trace, 0.05, continuous=0)
-    log("serving: capacity plain %.0f, continuous %.0f req/s; at %.0f req/s p50/p99 %.2f/%.2f ms vs plain %.2f/%.2f ms"
-        % (plain_cap, cont_cap, qps, cont["p50_ms"], cont["p99_ms"], plain["p50_ms"], plain["p99_ms"]))
+    points = {}
+    for name, qps in (("Q1", 0.5 * plain_cap), ("Q2", 0.8 * cont_cap)):
+        trace = gi.serving_trace(min_requests, qps=qps, seed=gi.SEED_SERVE)
+        cont = replay(hg, trace, 0.05, continuous=1)
+        plain = replay(hg, trace, 0.05, continuous=0)
+        points[name] = {"qps": qps, "continuous": cont, "plain": plain}
+        log("serving %s at %.0f req/s: continuous p50/p99 %.2f/%.2f ms (%.0f haf/s), plain %.2f/%.2f ms (%.0f haf/s)"
+            % (name, qps, cont["p50_ms"], cont["p99_ms"], cont["haf_per_s"], plain["p50_ms"], plain["p99_ms"],
+               plain["haf_per_s"]))
     return {"workload": "Poisson arrivals, haf/lhaf 50/50, n = 12 + 2j with P(j) ~ 0.7^j up to 44, "
-                        "GBS-style submatrices, seed %d" % gi.SEED_SERVE,
-            "qps": qps, "continuous": cont, "plain": plain,
-            "capacity_haf_per_s": {"continuous": cont_cap, "plain": plain_cap}}
+                        "GBS-style submatrices, seed %d, %d requests per point" % (gi.SEED_SERVE, min_requests),
+            "capacity_haf_per_s": {"continuous": cont_cap, "plain": plain_cap}, **points}
 
 
 def main():
@@ -296,7 +298,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-requests", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path "
@@ -381,7 +383,7 @@ def main():
     if not args.no_batched:
         line["batched"] = bench_batched(hg, gi)
     if not args.no_serving:
-        line["serving"] = bench_serving(hg, gi, args.serve_seconds)
+        line["serving"] = bench_serving(hg, gi, args.serve_requests)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(A, n, kind == hg.KIND_LHAF, args.cpu_seconds)
         line["cpu_baseline"]["gpu_over_cpu"] = line["value"] / line["cpu_baseline"]["value"]
