@@ -175,6 +175,23 @@ int haf_exact_i64(const int64_t* A, int n, int lda, int kind, uint32_t* magnitud
 int haf_modp_c(const int64_t* A, int n, int lda, int kind, const uint32_t* primes, int nprimes, uint32_t* residues);
 
 /*
+ * Hafnian of a low-rank matrix from its factor (App. C): G is n x r (row-major,
+ * leading dimension ldg >= r, complex, host memory), and the result is the
+ * hafnian of any matrix whose entries above the diagonal are those of G G^T
+ * (the hafnian ignores the diagonal).  With q(x) = prod_i (sum_j g_ij x_j) =
+ * sum_p lambda_p x^p, haf = sum over even exponent vectors e of
+ * lambda_e prod_j (e_j - 1)!!; the GPU expands q one factor at a time over the
+ * C(n + r - 1, r - 1) monomials of each degree, so the cost is polynomial in
+ * n for a fixed rank instead of 2^(n/2).  Synchronous; result as double-double;
+ * *cond (if not null) receives sum_e |lambda_e| prod (e_j - 1)!! / |haf|, the
+ * cancellation of the final sum.  n = 0 gives 1, odd n gives 0.  Errors:
+ * HAF_E_INVALID_ARG (null pointer, n < 0, r < 1, ldg < r), HAF_E_TOO_LARGE
+ * (n > 64, r > 8, or more than 2^28 monomials of degree n), HAF_E_NONFINITE,
+ * HAF_E_NOMEM, HAF_E_DEVICE.
+ */
+int haf_lowrank_c128(const haf_cplx* G, int n, int r, int ldg, haf_cplx2* out, double* cond);
+
+/*
  * Batched: count independent hafnians / loop hafnians of uneven sizes (the
  * per-matrix sums of Sec. 3.2, Eq. Pset; the paper names batched small-matrix
  * GPU work as the way forward in its conclusions).  Matrix t is stored densely

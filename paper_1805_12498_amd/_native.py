@@ -30,6 +30,7 @@ EXPORTS = (
     "haf_profile_enable", "haf_profile_read", "haf_batched_get_config", "haf_batched_set_config",
     "haf_batched_tune", "haf_batched_plan", "haf_batched_c128x2", "perm_c128", "perm_c128_dev",
     "haf_c128x2_dev_noalloc", "haf_exact_i64", "haf_modp_c", "haf_dd_c128x2_dev", "haf_dd_c128x2_host",
+    "haf_lowrank_c128",
 )
 
 
@@ -106,6 +107,7 @@ def load(path: str = LIB_PATH):
         "haf_exact_i64": ([vp, i, i, i, vp, ctypes.POINTER(i)], i),
         "haf_dd_c128x2_dev": ([vp, i, i, i, vp, vp], i),
         "haf_dd_c128x2_host": ([vp, i, i, i, vp], i),
+        "haf_lowrank_c128": ([vp, i, i, i, vp, ctypes.POINTER(ctypes.c_double)], i),
         "haf_modp_c": ([vp, i, i, i, vp, i, vp], i),
         "haf_terms_dev": ([vp, i, i, i, vp, i, vp, vp], i),
         "haf_batched_c128": ([vp, vp, vp, vp, i, vp, vp], i),
@@ -219,6 +221,21 @@ def haf_dev_dd(dA_ptr: int, n: int, lda: int, d_out_ptr: int, stream: int = 0, k
     """Enqueue the double-double mode on a device matrix; d_out receives 4 doubles."""
     check(load().haf_dd_c128x2_dev(ctypes.c_void_p(dA_ptr), n, lda, kind, ctypes.c_void_p(d_out_ptr),
                                    ctypes.c_void_p(stream)))
+
+
+def haf_lowrank(G):
+    """haf of the matrix with G G^T above the diagonal, from the n x r factor G (App. C).
+    Returns ((re_hi, re_lo, im_hi, im_lo), cond)."""
+    G = np.asarray(G)
+    if G.ndim != 2:
+        raise ValueError("expected an n x r factor")
+    G = np.ascontiguousarray(G, dtype=np.complex128)
+    n, r = G.shape
+    out = c128x2()
+    cond = ctypes.c_double(0.0)
+    ptr = G.ctypes.data if G.size else ctypes.addressof(ctypes.c_double(0.0))
+    check(load().haf_lowrank_c128(ctypes.c_void_p(ptr), n, r, max(r, 1), ctypes.byref(out), ctypes.byref(cond)))
+    return (out.re_hi, out.re_lo, out.im_hi, out.im_lo), cond.value
 
 
 def perm_host(W) -> complex:

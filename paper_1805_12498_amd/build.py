@@ -28,6 +28,7 @@ SOURCES = [
     "haf_noalloc.hip",
     "haf_kernels_modp.hip",
     "haf_kernels_dd.hip",
+    "haf_kernels_lowrank.hip",
     "haf_runtime.cpp",
     "haf_batched.cpp",
     "haf_server.cpp",
