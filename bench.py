@@ -34,25 +34,29 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6          # MI355X vector FP64: 256 CU x 128 flop/clk x 2.4 GHz
 
-# HBM bytes per launch of the coefficient kernel at n = 56 (haf), from rocprofv3
-# FETCH_SIZE and WRITE_SIZE runs calibrated against a 1 GiB copy
-# (profiles/coef_kernel_n56_haf_hbm_traffic.md), valid only while the kernel's
-# sources are the ones those counters were taken on.
-TRAFFIC_SOURCES = ("paper_1805_12498_amd/csrc/haf_coef_reg.hpp", "paper_1805_12498_amd/csrc/haf_kernels_reg.hip",
+# Counter figures of the coefficient kernel at n = 56 (haf), valid only while the
+# kernel's sources are the ones the counters were taken on (sha256 below):
+#  * HBM bytes per launch, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs calibrated
+#    against a 1 GiB device copy (profiles/coef_kernel_n56_haf_hbm_traffic.md);
+#  * FP64 flops per step as the SQ counters count them, 64 x (ADD_F64 + MUL_F64 +
+#    TRANS_F64 + 2 FMA_F64) wave instructions, which ignore the exec mask
+#    (profiles/coef_kernel_n56_haf_sq_counters.md).
+COUNTER_SOURCES = ("paper_1805_12498_amd/csrc/haf_coef_reg.hpp", "paper_1805_12498_amd/csrc/haf_kernels_reg.hip",
                    "paper_1805_12498_amd/csrc/haf_common.hpp")
-TRAFFIC_SHA256 = "2b87cef18583b1ffd60e1e7a917978546d5537b3017c48513a1412d03a0d89cc"
-TRAFFIC_N56_HAF_BYTES_PER_LAUNCH = 8.826e8
+COUNTER_SHA256 = "9063cab9eeaca26e2cbbb627b70507ee8843726a02167a6573ee7f60aab1a176"
+TRAFFIC_N56_HAF_BYTES_PER_LAUNCH = 8.825e8
+COUNTER_N56_HAF_FP64_FLOPS_PER_STEP = 2.197e14
 
 
-def coef_traffic(n, kind):
+def counters_valid(n, kind):
     import hashlib
     if n != 56 or kind != "haf":
-        return None
+        return False
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in COUNTER_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return TRAFFIC_N56_HAF_BYTES_PER_LAUNCH if h.hexdigest() == TRAFFIC_SHA256 else None
+    return h.hexdigest() == COUNTER_SHA256
 
 
 def log(*a):
@@ -367,7 +371,7 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": coef_traffic(n, args.kind),
+            "traffic": TRAFFIC_N56_HAF_BYTES_PER_LAUNCH if counters_valid(n, args.kind) else None,
             "traffic_unit": "bytes per launch",
             "kernel": "coefficient kernel (per-subset Hessenberg + characteristic polynomial)",
             "model": "(44/3) s^3 flops per subset of size s (+ 8 (N-1) s^2 for loop hafnians)",
@@ -376,6 +380,13 @@ def main():
             "share_of_step": prof["coef_ms"] * 1e-3 / secs,
         },
         "fp64_model_tflops_step": prof["coef_model_flops"] / secs / 1e12,
+        "fp64_counter": ({"flops_per_step": COUNTER_N56_HAF_FP64_FLOPS_PER_STEP,
+                          "tflops": COUNTER_N56_HAF_FP64_FLOPS_PER_STEP / (secs / args.steps) / 1e12,
+                          "frac_of_peak": COUNTER_N56_HAF_FP64_FLOPS_PER_STEP / (secs / args.steps) / 1e12
+                          / PEAK_FP64_TFLOPS,
+                          "note": "SQ_INSTS_VALU_{ADD,MUL,TRANS,FMA}_F64 wave instructions x 64 lanes (exec mask "
+                                  "ignored), per step, from the profile of this kernel source"}
+                         if counters_valid(n, args.kind) else None),
         "cpu_baseline": None,
     }
     if not args.no_configs:
