@@ -33,8 +33,9 @@
 //    slots and LDS offsets are static); the scaled Hessenberg entries g_{r,i} come
 //    from LDS, one read per complex multiply-add.
 //
-// The per-subset body lives in this header so that the one-size-class kernel
-// and the persistent batched kernel run exactly the same arithmetic.
+// The per-subset body lives in this header so that the one-size-class kernel,
+// the multi-chunk kernel and the shared batched / serving stage kernel run exactly
+// the same arithmetic.
 #pragma once
 #include "haf_common.hpp"
 
@@ -150,8 +151,8 @@ __device__ __forceinline__ void gather_tile(double2 (&hh)[R][C], uint32_t mk, in
 // from the neighbouring lane, or from `bin` (c_{i-1}[d0-1], written by the first
 // pass) for the lowest degree d0 of the call; `bout`, if given, receives
 // c_i[d_top] for every i.  Each step reads its column in chunks of 8 (the table is
-// followed by zeroed slack, so whole chunks are safe) and keeps the FMA pipeline fed
-// with two accumulators.
+// followed by zeroed slack, so whole chunks are safe), the first chunk one step
+// ahead, and keeps the FMA pipeline fed with two accumulators.
 template <int S, int SPLIT, int R0>
 __device__ __forceinline__ double2 charpoly_lanes(const double2* __restrict__ gt, int d, int h, int dlo,
                                                   const double2* __restrict__ bin, double2* __restrict__ bout,
@@ -163,12 +164,30 @@ __device__ __forceinline__ double2 charpoly_lanes(const double2* __restrict__ gt
     // rows r = R0 + k*SPLIT + h; c_{R0}... start from c_i = 0 at these degrees, except c_0 = 1
     if (R0 == 0 && h == 0 && d == 0) cr[0] = cone();
     double2 prev = (R0 == 0 && d == 0) ? cone() : cz();
+    constexpr int I0 = R0 > 0 ? R0 : 1;
+    // the first chunk of each step's column is read one step ahead, so its LDS latency
+    // overlaps the previous step's multiply-adds and reduction (the table is read-only here)
+    double2 gnext[8];
 #pragma unroll
-    for (int i = (R0 > 0 ? R0 : 1); i <= S; ++i) {
+    for (int k = 0; k < 8; ++k)
+        if (k < K) gnext[k] = gt[(I0 - 1) * I0 / 2 + R0 + k * SPLIT + h];
+#pragma unroll
+    for (int i = I0; i <= S; ++i) {
         const int nk = (i - R0 + SPLIT - 1) / SPLIT;    // slots that may hold r < i (compile-time)
+        double2 gcur[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) gcur[k] = gnext[k];
+        if (i < S) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k < K) gnext[k] = gt[i * (i + 1) / 2 + R0 + k * SPLIT + h];
+        }
         double2 acc[2] = { cz(), cz() };
 #pragma unroll
-        for (int c0 = 0; c0 < nk; c0 += 8) {
+        for (int k = 0; k < 8; ++k)
+            if (k < K && k < nk) cfma(acc[k & 1], gcur[k], cr[k]);
+#pragma unroll
+        for (int c0 = 8; c0 < nk; c0 += 8) {
             double2 gv[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k)
@@ -194,8 +213,8 @@ __device__ __forceinline__ double2 charpoly_lanes(const double2* __restrict__ gt
         if (bout && i < S && d == dtop && h == 0) bout[i] = ci;   // bout has S entries
         prev = ci;
         __builtin_amdgcn_s_setprio(0);
-        // keep each step's reads within the step: hoisting them across steps only
-        // raises register pressure (and occupancy is what hides their latency)
+        // the step's other reads stay within it: hoisting them further ahead only raises
+        // register pressure (and occupancy is what hides their latency)
         __builtin_amdgcn_sched_barrier(0);
     }
     return prev;
