@@ -189,7 +189,7 @@ def bench_configs(hg, gi):
         ref = int(g["n56_graph_exact"]["exact"])
         c3b["exact_path_equals_oracle"] = exact == ref
         c3b["relerr"] = abs(complex(got) - ref) / ref
-        c3b["relerr_vs"] = "the oracle's exact count (sum over F_p for six 31-bit primes, CRT)"
+        c3b["relerr_vs"] = "the oracle's exact count (sum over F_p for four 31-bit primes, CRT, and a check prime)"
     else:
         c3b["relerr_vs_exact_path"] = abs(complex(got) - exact) / abs(exact)
     out["C3b_n56_graph"] = c3b

@@ -114,7 +114,8 @@ def test_grid_7x8_exact(hg):
 
 def test_random_graph_n56_exact(hg):
     """The 56-vertex 0/1 graph, edge probability 1/2, seed 5602: the exact matching count
-    against the oracle's (its own sum over five 31-bit primes plus a check prime, CRT)."""
+    against the oracle's (its own sum over four 31-bit primes plus a check prime, CRT; the
+    product of the four bounds the count of any 56-vertex graph, 55!! < 2^123)."""
     if "n56_graph_exact" not in GOLD:
         pytest.skip("the oracle's exact count of G(56, 1/2) seed 5602 is not stored yet")
     G = gi.random_graph(56, 0.5, gi.SEED_N56_GRAPH).real.astype(np.int64)
