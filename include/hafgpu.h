@@ -333,8 +333,9 @@ typedef struct {
 
 typedef struct {
     uint64_t ticket;
-    int status;                 /* HAF_OK, HAF_E_DEVICE, or HAF_E_STATE if the server
-                                   stopped before admitting the request                 */
+    int status;                 /* HAF_OK, HAF_E_DEVICE (a launch of its tick failed),
+                                   or HAF_E_STATE if the server stopped before
+                                   admitting the request                                */
     int n, kind;
     haf_cplx value;
     double t_submit, t_admit, t_done;   /* seconds on the host steady clock (haf_now) */
@@ -356,6 +357,15 @@ int haf_server_poll(haf_server* s, haf_result* out, int max, int* n_out);
 int haf_server_drain(haf_server* s);
 /* Stop the scheduler and free its device memory (pending requests fail). */
 void haf_server_destroy(haf_server* s);
+/* Failure handling.  When a tick (or, in the plain server, a request's launch)
+ * reports a HIP error, the scheduler waits for everything enqueued on its
+ * stream, fails every admitted request with HAF_E_DEVICE, replaces the stream
+ * with a new one and goes on admitting the queued requests.  This test hook
+ * makes the next `count` completed ticks (plain server: requests) take that
+ * path although their launches succeeded, so the recovery can be exercised
+ * from the host without a device fault.  Returns HAF_E_INVALID_ARG for a null
+ * server or a negative count. */
+int haf_server_debug_fail_ticks(haf_server* s, int count);
 /* Seconds on the steady clock used for the t_* fields. */
 double haf_now(void);
 

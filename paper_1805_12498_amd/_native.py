@@ -30,7 +30,7 @@ EXPORTS = (
     "haf_profile_enable", "haf_profile_read", "haf_batched_get_config", "haf_batched_set_config",
     "haf_batched_tune", "haf_batched_plan", "haf_batched_c128x2", "perm_c128", "perm_c128_dev",
     "haf_c128x2_dev_noalloc", "haf_exact_i64", "haf_modp_c", "haf_dd_c128x2_dev", "haf_dd_c128x2_host",
-    "haf_lowrank_c128",
+    "haf_lowrank_c128", "haf_server_debug_fail_ticks",
 )
 
 
@@ -119,6 +119,7 @@ def load(path: str = LIB_PATH):
         "haf_server_submit": ([vp, vp, i, i, i, ctypes.POINTER(u64)], i),
         "haf_server_poll": ([vp, vp, i, ctypes.POINTER(i)], i),
         "haf_server_drain": ([vp], i),
+        "haf_server_debug_fail_ticks": ([vp, i], i),
         "haf_server_destroy": ([vp], None),
         "haf_now": ([], ctypes.c_double),
         "haf_profile_enable": ([i], i),
@@ -388,6 +389,10 @@ class Server:
 
     def drain(self):
         check(self._lib.haf_server_drain(self._h))
+
+    def debug_fail_ticks(self, count: int):
+        """Test hook: handle the next `count` completed ticks as failed launches."""
+        check(self._lib.haf_server_debug_fail_ticks(self._h, count))
 
     def close(self):
         if self._h:

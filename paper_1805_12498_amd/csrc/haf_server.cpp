@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -158,6 +159,10 @@ struct haf_server {
     std::string start_error;
     bool started = false;
     std::condition_variable cv_start;
+    // test hook: this many of the next completed ticks (or plain-server requests)
+    // are handled as failed launches
+    std::atomic<int> inject_fail{0};
+    bool broken = false;                    // no stream after a failed reset: requests fail at once
 };
 
 namespace {
@@ -436,6 +441,9 @@ bool enqueue_tick(haf_server* s, int ti, int* rc_out) {
     return true;
 }
 
+// A launch failed: wait for everything enqueued on the stream (no work may
+// outlive the device memory of its request), fail every admitted request, and
+// go on with a fresh stream.  Requests still queued are admitted afterwards.
 void fail_all(haf_server* s, int status) {
     (void)hipStreamSynchronize(s->stream);
     for (int t = 0; t < kTicksInFlight; ++t) {
@@ -446,6 +454,23 @@ void fail_all(haf_server* s, int status) {
     std::deque<Request*> act;
     act.swap(s->active);
     for (Request* r : act) finish(s, r, status, nullptr);
+    release_stream_workspace(s->stream);     // the plain server's single-matrix workspaces
+    (void)hipStreamDestroy(s->stream);
+    s->stream = nullptr;
+    (void)hipGetLastError();                 // clear a sticky launch error before the new stream
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+        s->stream = nullptr;
+        s->broken = true;
+    }
+}
+
+// hipEventQuery, or a failure forced by the test hook once the event has completed
+hipError_t query_done(haf_server* s, hipEvent_t ev) {
+    const hipError_t e = hipEventQuery(ev);
+    if (e != hipSuccess) return e;
+    int k = s->inject_fail.load();
+    while (k > 0 && !s->inject_fail.compare_exchange_weak(k, k - 1)) {}
+    return k > 0 ? hipErrorLaunchFailure : hipSuccess;
 }
 
 void scheduler(haf_server* s) {
@@ -506,6 +531,10 @@ void scheduler(haf_server* s) {
             s->free_slots.pop_back();
             r->t_admit = now_seconds();
             progress = true;
+            if (s->broken && r->cval == kGroupComputed) {    // no stream to run it on
+                finish(s, r, HAF_E_DEVICE, nullptr);
+                continue;
+            }
             if (r->cval != kGroupComputed) {                    // n = 0 or odd-n haf
                 const double v[4] = { r->cval == kGroupConstOne ? 1.0 : 0.0, 0.0, 0.0, 0.0 };
                 finish(s, r, HAF_OK, v);
@@ -539,7 +568,7 @@ void scheduler(haf_server* s) {
             // ---- completed ticks, in launch order
             while (!s->inflight.empty()) {
                 TickSlot& T = s->ticks[s->inflight.front()];
-                const hipError_t e = hipEventQuery(T.done);
+                const hipError_t e = query_done(s, T.done);
                 if (e == hipErrorNotReady) break;
                 if (e != hipSuccess) {
                     fail_all(s, HAF_E_DEVICE);
@@ -567,12 +596,16 @@ void scheduler(haf_server* s) {
                 }
             }
         } else if (s->plain_cur) {
-            const hipError_t e = hipEventQuery(s->plain_ev);
+            const hipError_t e = query_done(s, s->plain_ev);
             if (e != hipErrorNotReady) {
                 Request* r = s->plain_cur;
                 s->plain_cur = nullptr;
-                if (e == hipSuccess) finish(s, r, HAF_OK, s->plain_host);
-                else finish(s, r, HAF_E_DEVICE, nullptr);
+                if (e == hipSuccess) {
+                    finish(s, r, HAF_OK, s->plain_host);
+                } else {
+                    s->active.push_back(r);          // fail_all fails it and resets the stream
+                    fail_all(s, HAF_E_DEVICE);
+                }
                 progress = true;
             }
         }
@@ -681,6 +714,13 @@ int haf_server_poll(haf_server* s, haf_result* out, int max, int* n_out) {
         s->results.pop_front();
     }
     *n_out = k;
+    return HAF_OK;
+}
+
+int haf_server_debug_fail_ticks(haf_server* s, int count) {
+    clear_error();
+    if (!s || count < 0) return set_error(HAF_E_INVALID_ARG, "null server or negative count");
+    s->inject_fail.store(count);
     return HAF_OK;
 }
 

@@ -173,3 +173,50 @@ def test_destroy_with_pending_requests(hg):
     for _, kind, A in gi.serving_trace(40, qps=1e4, seed=13, nmax=30):
         srv.submit(A, kind)
     srv.close()
+
+
+@pytest.mark.parametrize("continuous", [1, 0])
+def test_failed_launch_recovery(hg, continuous):
+    """A tick whose launch fails (forced from the host by the test hook after the launch
+    really succeeded, so the device never faults) fails the admitted requests with
+    HAF_E_DEVICE; the server replaces its stream and the next requests complete, bitwise
+    equal to the single-matrix path."""
+    srv = hg.Server(continuous=continuous)
+    try:
+        srv.debug_fail_ticks(1)
+        first = gi.serving_trace(8, qps=1e4, seed=17, nmax=20)
+        tickets = {}
+        for _, kind, A in first:
+            tickets[srv.submit(A, kind)] = (kind, A)
+        srv.drain()
+        res1 = srv.poll(64)
+        assert len(res1) == len(first)
+        failed = [r for r in res1 if r.status == 5]
+        assert failed, "the forced failure must fail at least the requests of its tick"
+        for r in res1:
+            assert r.status in (0, 5)
+            if r.status == 0:
+                kind, A = tickets[r.ticket]
+                assert complex(r.value.re, r.value.im) == hg.haf_host(A, kind)
+        second = gi.serving_trace(12, qps=1e4, seed=18, nmax=24)
+        for _, kind, A in second:
+            tickets[srv.submit(A, kind)] = (kind, A)
+        srv.drain()
+        res2 = srv.poll(64)
+        assert len(res2) == len(second)
+        for r in res2:
+            kind, A = tickets[r.ticket]
+            assert r.status == 0
+            assert complex(r.value.re, r.value.im) == hg.haf_host(A, kind)
+    finally:
+        srv.close()
+
+
+def test_debug_hook_rejects_bad_arguments(hg):
+    from paper_1805_12498_amd._native import HafError
+    srv = hg.Server()
+    try:
+        with pytest.raises(HafError, match="INVALID_ARG"):
+            srv.debug_fail_ticks(-1)
+    finally:
+        srv.close()
