@@ -271,6 +271,7 @@ static int run_grouped(const double2* dA, const int64_t* offs, const int32_t* ns
                        const std::vector<int>& list, double2* d_out, double* d_out_dd, hipStream_t st,
                        const haf_batched_config& cfg) {
     if (list.empty()) return HAF_OK;
+    HostRange range("hafgpu: batched stage launches");
     BatchWS* w = nullptr;
     int rc = batch_ws(st, &w);
     if (rc) return rc;
@@ -387,6 +388,7 @@ double item_cost(int n, int kind) {
 
 int run_batched(const double2* dA, const int64_t* offs, const int32_t* ns, const uint8_t* kinds, int count,
                 double2* d_out, double* d_out_dd, hipStream_t st, const haf_batched_config& cfg) {
+    HostRange range("hafgpu: batched call");
     int rc = check_batch_args(dA, offs, ns, kinds, count, d_out ? (const void*)d_out : (const void*)d_out_dd);
     if (rc || count == 0) return rc;
     int dev = 0;

@@ -411,6 +411,7 @@ int enqueue_haf(const double2* dA, int n, int lda, int kind, double* out_dd, dou
 
 // Device-side entry: handles n = 0, odd n and the padding for odd-n lhaf.
 int run_dev(const double2* dA, int n, int lda, int kind, double* out_dd, double2* out, hipStream_t st, int prec) {
+    HostRange range("hafgpu: enqueue one matrix");
     int rc = ensure_device(nullptr);
     if (rc) return rc;
     if (n == 0) return hip_check(launch_write_const(st, 1.0, out_dd, out), "write kernel launch");

@@ -1,6 +1,7 @@
 // Internal host-side interfaces shared by the runtime, batched and serving code.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 
 #include <string>
@@ -62,5 +63,13 @@ double coef_model_flops(int s, int N, bool loops);
 void release_batch_workspaces();
 void release_stream_workspace(hipStream_t st);   // free the workspace kept for one stream (current device)
 int noalloc_setup(int dev);   // device address of the allocation-free entry point's scratch array
+
+// A named range of host work for rocprofv3's marker trace (a no-op without a tool attached).
+struct HostRange {
+    explicit HostRange(const char* what) { roctxRangePushA(what); }
+    ~HostRange() { roctxRangePop(); }
+    HostRange(const HostRange&) = delete;
+    HostRange& operator=(const HostRange&) = delete;
+};
 
 }  // namespace hafgpu

@@ -250,6 +250,7 @@ int grow_slot(TickSlot& t, size_t need, hipStream_t st) {
 
 // Build and enqueue one tick into slot `ti`.  Returns false if there was no work.
 bool enqueue_tick(haf_server* s, int ti, int* rc_out) {
+    HostRange range("hafgpu: server tick");
     TickSlot& T = s->ticks[ti];
     *rc_out = HAF_OK;
     const haf_server_config& c = s->cfg;
