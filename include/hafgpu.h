@@ -62,7 +62,15 @@ const char* haf_last_error(void);
 const char* haf_version(void);
 
 /* Select and initialise a HIP device for this thread's subsequent calls
- * (optional: the current device is initialised lazily). */
+ * (optional: the current device is initialised lazily).  Also loads the batched
+ * configuration cached for this device, if HAF_AUTOTUNE_CACHE names a file that
+ * has one (haf_batched_load_cache).
+ *
+ * Environment (read by the library):
+ *   HAF_AUTOTUNE_CACHE  file of tuned batched configurations, one per device;
+ *   HAF_ARENA_BYTES     default server arena (integer, optional K/M/G suffix);
+ *   HAF_KERNEL_PATH     initial kernel path (0, 1 or 2; haf_set_kernel_path);
+ *   HAF_DEBUG           non-zero: every error is also printed to stderr. */
 int haf_init(int device);
 
 /* One-line description of the device and kernel configuration into buf. */
@@ -245,10 +253,19 @@ int haf_batched_set_config(const haf_batched_config* cfg);
  * receives the results) under a coordinate search (span 1..16 with the full
  * layout table, then the other table, then 1, 2, 4 streams, then grouped = 0),
  * times each run with HIP events on `stream`, makes the fastest the current
- * configuration and returns it in *best and its time in *best_ms.  Synchronous. */
+ * configuration and returns it in *best and its time in *best_ms.  Synchronous.
+ * If HAF_AUTOTUNE_CACHE names a file, the result is also stored there as this
+ * device's entry (one text line "<arch>:<CUs> table span streams grouped
+ * coef_budget_mb", replacing an older one); HAF_E_STATE if the file cannot be
+ * written (the configuration is applied all the same). */
 int haf_batched_tune(const haf_cplx* dA_packed, const int64_t* h_offsets, const int32_t* h_n,
                      const uint8_t* h_kind, int count, haf_cplx* d_out, void* stream, haf_batched_config* best,
                      double* best_ms);
+/* Make the current device's entry of the HAF_AUTOTUNE_CACHE file the current
+ * batched configuration.  HAF_E_STATE if the variable is unset or the file has
+ * no entry for this device, HAF_E_INVALID_ARG for a malformed line or values
+ * out of range, HAF_E_DEVICE without a device. */
+int haf_batched_load_cache(void);
 /* Host-only view of the shared launches under the current configuration (no
  * device needed).  launches receives 8 int64 per launch, in launch order:
  * (what: 0 coefficients / 1 series, layout, loops, blocks, first chunk, chunks,

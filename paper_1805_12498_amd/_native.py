@@ -30,7 +30,7 @@ EXPORTS = (
     "haf_profile_enable", "haf_profile_read", "haf_batched_get_config", "haf_batched_set_config",
     "haf_batched_tune", "haf_batched_plan", "haf_batched_c128x2", "perm_c128", "perm_c128_dev",
     "haf_c128x2_dev_noalloc", "haf_exact_i64", "haf_modp_c", "haf_dd_c128x2_dev", "haf_dd_c128x2_host",
-    "haf_lowrank_c128", "haf_server_debug_fail_ticks",
+    "haf_lowrank_c128", "haf_server_debug_fail_ticks", "haf_batched_load_cache",
 )
 
 
@@ -120,6 +120,7 @@ def load(path: str = LIB_PATH):
         "haf_server_poll": ([vp, vp, i, ctypes.POINTER(i)], i),
         "haf_server_drain": ([vp], i),
         "haf_server_debug_fail_ticks": ([vp, i], i),
+        "haf_batched_load_cache": ([], i),
         "haf_server_destroy": ([vp], None),
         "haf_now": ([], ctypes.c_double),
         "haf_profile_enable": ([i], i),
@@ -313,6 +314,12 @@ def batched_tune(dA_ptr: int, offsets, sizes, kinds, d_out_ptr: int, stream: int
                                   len(sizes), ctypes.c_void_p(d_out_ptr), ctypes.c_void_p(stream),
                                   ctypes.byref(c), ctypes.byref(ms)))
     return {f: getattr(c, f) for f, _ in BatchedConfig._fields_}, ms.value
+
+
+def batched_load_cache() -> dict:
+    """Make this device's entry of the HAF_AUTOTUNE_CACHE file the batched configuration."""
+    check(load().haf_batched_load_cache())
+    return batched_config()
 
 
 def batched_plan(sizes, kinds):

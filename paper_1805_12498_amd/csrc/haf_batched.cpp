@@ -16,7 +16,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
+#include <unistd.h>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -67,6 +72,78 @@ static int stage_layout(int table, int s) {
     for (int l = fine; l < reg_layout_count(); ++l)
         if (reg_layout_sm(l) % 8 == 0) return l;
     return fine;
+}
+
+// ------------------------------------------------------------------ autotune cache
+// A text file named by HAF_AUTOTUNE_CACHE, one line per device:
+//   <arch>:<compute units> <table> <span> <streams> <grouped> <coef_budget_mb>
+// written by the autotuner and read by haf_batched_load_cache (and haf_init).
+static std::string device_key() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return std::string();
+    std::string arch = p.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    return arch + ":" + std::to_string(p.multiProcessorCount);
+}
+
+static int cache_read(const char* path, const std::string& key, haf_batched_config* out, bool* found) {
+    *found = false;
+    std::ifstream f(path);
+    if (!f) return HAF_OK;                                  // no file yet: nothing cached
+    std::string line;
+    for (int ln = 1; std::getline(f, line); ++ln) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream is(line);
+        std::string k;
+        haf_batched_config c{};
+        if (!(is >> k >> c.table >> c.span >> c.streams >> c.grouped >> c.coef_budget_mb))
+            return set_error(HAF_E_INVALID_ARG, "%s:%d: malformed autotune cache line", path, ln);
+        if (k != key) continue;
+        if (check_config(c)) return set_error(HAF_E_INVALID_ARG, "%s:%d: %s", path, ln, last_error());
+        *out = c;
+        *found = true;
+    }
+    return HAF_OK;
+}
+
+static int cache_write(const char* path, const std::string& key, const haf_batched_config& c) {
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (f && std::getline(f, line)) {
+            std::istringstream is(line);
+            std::string k;
+            if (!line.empty() && line[0] != '#' && (is >> k) && k == key) continue;
+            keep.push_back(line);
+        }
+    }
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+    {
+        std::ofstream f(tmp);
+        if (!f) return set_error(HAF_E_STATE, "cannot write autotune cache %s", tmp.c_str());
+        for (const std::string& l : keep) f << l << "\n";
+        f << key << ' ' << c.table << ' ' << c.span << ' ' << c.streams << ' ' << c.grouped << ' '
+          << c.coef_budget_mb << "\n";
+        if (!f) return set_error(HAF_E_STATE, "cannot write autotune cache %s", tmp.c_str());
+    }
+    if (std::rename(tmp.c_str(), path) != 0) return set_error(HAF_E_STATE, "cannot replace autotune cache %s", path);
+    return HAF_OK;
+}
+
+int batched_load_cache(bool quiet) {
+    const char* path = std::getenv("HAF_AUTOTUNE_CACHE");
+    if (!path || !*path) return quiet ? HAF_OK : set_error(HAF_E_STATE, "HAF_AUTOTUNE_CACHE is not set");
+    const std::string key = device_key();
+    if (key.empty()) return set_error(HAF_E_DEVICE, "no current device");
+    haf_batched_config c{};
+    bool found = false;
+    const int rc = cache_read(path, key, &c, &found);
+    if (rc) return rc;
+    if (!found) return quiet ? HAF_OK : set_error(HAF_E_STATE, "no entry for %s in %s", key.c_str(), path);
+    set_batch_config(c);
+    return HAF_OK;
 }
 
 // ------------------------------------------------------------------ planner
@@ -560,7 +637,18 @@ int haf_batched_tune(const haf_cplx* dA_packed, const int64_t* h_offsets, const 
     set_batch_config(pick);
     if (best) *best = pick;
     if (best_ms) *best_ms = pick_ms;
+    const char* path = std::getenv("HAF_AUTOTUNE_CACHE");
+    if (path && *path) {
+        const std::string key = device_key();
+        if (key.empty()) return set_error(HAF_E_DEVICE, "no current device");
+        return cache_write(path, key, pick);
+    }
     return HAF_OK;
+}
+
+int haf_batched_load_cache(void) {
+    clear_error();
+    return batched_load_cache(false);
 }
 
 int haf_batched_plan(const int32_t* h_n, const uint8_t* h_kind, int count, int64_t* launches, int max_launches,

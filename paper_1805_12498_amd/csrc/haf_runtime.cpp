@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -30,7 +31,21 @@
 namespace hafgpu {
 
 static thread_local std::string g_err;
-static int g_kernel_path = 0;
+// HAF_KERNEL_PATH (0, 1 or 2) selects the initial kernel path
+static int initial_kernel_path() {
+    const char* e = std::getenv("HAF_KERNEL_PATH");
+    const int p = e ? std::atoi(e) : 0;
+    return (p >= 0 && p <= 2) ? p : 0;
+}
+static int g_kernel_path = initial_kernel_path();
+
+static bool debug_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("HAF_DEBUG");
+        return e && *e && std::strcmp(e, "0") != 0;
+    }();
+    return on;
+}
 
 int set_error(int code, const char* fmt, ...) {
     char buf[512];
@@ -39,6 +54,7 @@ int set_error(int code, const char* fmt, ...) {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_err = buf;
+    if (debug_enabled()) std::fprintf(stderr, "hafgpu: error %d: %s\n", code, buf);
     return code;
 }
 void clear_error() { g_err.clear(); }
@@ -577,8 +593,10 @@ const char* haf_version(void) { return "hafgpu 0.1 (gfx950)"; }
 int haf_init(int device) {
     clear_error();
     if (hipSetDevice(device) != hipSuccess) return set_error(HAF_E_DEVICE, "hipSetDevice(%d) failed", device);
-    const int rc = ensure_device(nullptr);
-    return rc ? rc : noalloc_setup(device);
+    int rc = ensure_device(nullptr);
+    if (!rc) rc = noalloc_setup(device);
+    if (!rc) rc = batched_load_cache(true);
+    return rc;
 }
 
 int haf_device_info(char* buf, int buflen) {

@@ -63,6 +63,7 @@ double coef_model_flops(int s, int N, bool loops);
 void release_batch_workspaces();
 void release_stream_workspace(hipStream_t st);   // free the workspace kept for one stream (current device)
 int noalloc_setup(int dev);   // device address of the allocation-free entry point's scratch array
+int batched_load_cache(bool quiet);   // batched configuration from HAF_AUTOTUNE_CACHE, if it has this device
 
 // A named range of host work for rocprofv3's marker trace (a no-op without a tool attached).
 struct HostRange {

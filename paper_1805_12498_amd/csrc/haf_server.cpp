@@ -32,6 +32,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -633,6 +634,14 @@ void haf_server_default_config(haf_server_config* cfg) {
     if (!cfg) return;
     cfg->device = 0;
     cfg->arena_bytes = (int64_t)1 << 30;
+    // HAF_ARENA_BYTES overrides the arena size: an integer, optionally followed by K, M or G
+    if (const char* e = std::getenv("HAF_ARENA_BYTES")) {
+        char* end = nullptr;
+        long long v = std::strtoll(e, &end, 10);
+        const char u = end ? *end : 0;
+        v <<= (u == 'K' || u == 'k') ? 10 : (u == 'M' || u == 'm') ? 20 : (u == 'G' || u == 'g') ? 30 : 0;
+        if (v > 0) cfg->arena_bytes = v;
+    }
     cfg->max_active = 256;
     cfg->max_queue = 1 << 20;
     cfg->tick_flops = 2.0e10;

@@ -52,3 +52,21 @@ def test_library_targets_gfx950():
 def test_version_without_gpu(lib):
     lib.haf_version.restype = ctypes.c_char_p
     assert lib.haf_version().startswith(b"hafgpu")
+
+
+@pytest.mark.parametrize("value,expect", [("65536", 65536), ("64M", 64 << 20), ("2G", 2 << 30), ("junk", 1 << 30)])
+def test_server_arena_from_environment(lib, monkeypatch, value, expect):
+    """HAF_ARENA_BYTES sets the default server arena (host-only call, no device)."""
+    from paper_1805_12498_amd._native import ServerConfig
+    monkeypatch.setenv("HAF_ARENA_BYTES", value)
+    cfg = ServerConfig()
+    lib.haf_server_default_config(ctypes.byref(cfg))
+    assert cfg.arena_bytes == expect
+
+
+def test_batched_cache_needs_its_variable(lib, monkeypatch):
+    """Without HAF_AUTOTUNE_CACHE the cache loader reports HAF_E_STATE (host-only)."""
+    monkeypatch.delenv("HAF_AUTOTUNE_CACHE", raising=False)
+    lib.haf_last_error.restype = ctypes.c_char_p
+    assert lib.haf_batched_load_cache() == 8
+    assert b"HAF_AUTOTUNE_CACHE" in lib.haf_last_error()

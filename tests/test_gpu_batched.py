@@ -224,3 +224,43 @@ def test_autotuner(hg):
     again = run_batch(hg, mats, kinds)
     assert np.array_equal(tuned, again)
     hg.set_batched_config()
+
+
+def test_autotune_cache(hg, tmp_path, monkeypatch):
+    """HAF_AUTOTUNE_CACHE: the autotuner stores its choice as this device's line of the
+    file (replacing an older one), and haf_batched_load_cache makes it current again."""
+    import torch
+    from paper_1805_12498_amd._native import HafError
+    path = tmp_path / "tune.txt"
+    monkeypatch.delenv("HAF_AUTOTUNE_CACHE", raising=False)
+    with pytest.raises(HafError, match="STATE"):
+        hg.batched_load_cache()
+    monkeypatch.setenv("HAF_AUTOTUNE_CACHE", str(path))
+    with pytest.raises(HafError, match="STATE"):        # no file yet: no entry for this device
+        hg.batched_load_cache()
+    mats = gi.gbs_batch(64, seed=33)
+    flat, offs, sizes = gi.pack(mats)
+    kinds = np.ones(len(mats), dtype=np.uint8)
+    dA = torch.from_numpy(flat).cuda()
+    out = torch.zeros(len(mats), dtype=torch.complex128, device="cuda")
+    keep = hg.batched_config()
+    try:
+        path.write_text("# tuned batched configurations\nother:1 1 2 1 0 64\n")
+        cfg, _ = hg.batched_tune(dA.data_ptr(), offs, sizes, kinds, out.data_ptr(), 0)
+        hg.batched_tune(dA.data_ptr(), offs, sizes, kinds, out.data_ptr(), 0)   # replaces its own line
+        lines = path.read_text().splitlines()
+        assert lines[:2] == ["# tuned batched configurations", "other:1 1 2 1 0 64"]
+        mine = [ln for ln in lines[2:]]
+        assert len(mine) == 1 and mine[0].split()[0].startswith("gfx")
+        hg.set_batched_config(table=1 - cfg["table"], span=3, streams=1, grouped=1, coef_budget_mb=128)
+        got = hg.batched_load_cache()
+        key, *vals = mine[0].split()
+        assert [got[f] for f in ("table", "span", "streams", "grouped", "coef_budget_mb")] == [int(v) for v in vals]
+        path.write_text("%s 0 0 1 1 64\n" % key)           # span 0 is out of range
+        with pytest.raises(HafError, match="INVALID_ARG"):
+            hg.batched_load_cache()
+        path.write_text("%s 0 x\n" % key)
+        with pytest.raises(HafError, match="INVALID_ARG"):
+            hg.batched_load_cache()
+    finally:
+        hg.set_batched_config(**keep)
