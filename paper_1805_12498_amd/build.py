@@ -87,6 +87,50 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_host_sanitized(out_dir: str) -> str:
+    """Host code only (no device code objects), with AddressSanitizer and
+    UndefinedBehaviorSanitizer, into out_dir/libhafgpu_host_asan.so: for CPU tests of
+    the host-side logic (planner, configuration, argument checks, error paths).  A
+    process that loads it must preload the sanitizer runtime (asan_runtime())."""
+    os.makedirs(out_dir, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+    flags = ["-O1", "-g", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "--offload-host-only",
+             "-I" + INCLUDE, "-I" + CSRC] + san
+
+    def one(src):
+        obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        cmd = [hipcc()] + flags + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+        return obj
+
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    with cf.ThreadPoolExecutor(min(len(srcs), max(1, min(8, os.cpu_count() or 1)))) as ex:
+        objs = list(ex.map(one, srcs))
+    lib = os.path.join(out_dir, "libhafgpu_host_asan.so")
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "--offload-host-only", "-shared-libsan"] + san + [
+        "-o", lib] + objs + ["-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx",
+                             "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+    return lib
+
+
+def asan_runtime() -> str:
+    """The compiler's shared AddressSanitizer runtime (to preload)."""
+    r = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        import glob
+        hits = sorted(glob.glob(os.path.join(ROCM, "llvm", "lib", "clang", "*", "lib", "*", "libclang_rt.asan-x86_64.so")))
+        path = hits[-1] if hits else ""
+    return path
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
