@@ -263,9 +263,14 @@ def replay(hg, trace, t_offset, **cfg):
     lat = np.array([r.t_done - arrival[r.ticket] for r in results])
     assert all(r.status == 0 for r in results) and len(results) == len(trace)
     span = end - start
+    # latency histogram: counts per power-of-two bucket of milliseconds, [2^(k-1), 2^k) for key 2^k
+    edges = 2.0 ** np.arange(-6, 12)
+    counts = np.histogram(lat * 1e3, bins=np.concatenate(([0.0], edges, [np.inf])))[0]
+    hist = {("<%g" % e if k < len(edges) else ">=%g" % edges[-1]): int(c)
+            for k, (e, c) in enumerate(zip(list(edges) + [np.inf], counts)) if c}
     return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3), "haf_per_s": len(trace) / span, "requests": len(trace),
-            "seconds": span}
+            "seconds": span, "latency_ms_histogram": hist}
 
 
 def bench_serving(hg, gi, min_requests=10000):
@@ -303,6 +308,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--jsonl", default=None,
+                    help="append the result line, with run metadata, to this JSON-lines file")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path "
@@ -399,6 +406,30 @@ def main():
         line["cpu_baseline"] = cpu_baseline(A, n, kind == hg.KIND_LHAF, args.cpu_seconds)
         line["cpu_baseline"]["gpu_over_cpu"] = line["value"] / line["cpu_baseline"]["value"]
     print(json.dumps(line), flush=True)
+    if args.jsonl:
+        append_jsonl(args.jsonl, line, A, hg, vars(args))
+
+
+def append_jsonl(path, line, A, hg, args):
+    """One record per run: the result line plus when, where and on what it ran."""
+    import hashlib
+    import platform
+    import subprocess
+    rec = dict(line)
+    rec["run"] = {
+        "utc": time.strftime("%Y-%m-%dT%H:%M:%SZ", time.gmtime()),
+        "args": args,
+        "input_sha256": hashlib.sha256(A.tobytes()).hexdigest(),
+        "device": hg.device_info(),
+        "host": {"cpu": cpu_model(), "threads": os.cpu_count(), "python": platform.python_version()},
+    }
+    try:
+        rec["run"]["commit"] = subprocess.run(["git", "rev-parse", "HEAD"], cwd=ROOT, capture_output=True,
+                                              text=True, timeout=10).stdout.strip() or None
+    except (OSError, subprocess.SubprocessError):
+        rec["run"]["commit"] = None
+    with open(path, "a") as f:
+        f.write(json.dumps(rec) + "\n")
 
 
 if __name__ == "__main__":
