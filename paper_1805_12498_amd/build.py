@@ -88,14 +88,15 @@ def build(verbose: bool = False) -> str:
 
 
 def build_host_sanitized(out_dir: str) -> str:
-    """Host code only (no device code objects), with AddressSanitizer and
-    UndefinedBehaviorSanitizer, into out_dir/libhafgpu_host_asan.so: for CPU tests of
-    the host-side logic (planner, configuration, argument checks, error paths).  A
-    process that loads it must preload the sanitizer runtime (asan_runtime())."""
+    """The library with its host code under AddressSanitizer and
+    UndefinedBehaviorSanitizer (device code unsanitized and unoptimised, to build
+    fast), into out_dir/libhafgpu_host_asan.so: for CPU tests of the host-side logic
+    (planner, configuration, argument checks, error paths).  A process that loads
+    it must preload the sanitizer runtime (asan_runtime())."""
     os.makedirs(out_dir, exist_ok=True)
     san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
-    flags = ["-O1", "-g", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "--offload-host-only",
+    flags = ["-O1", "-g", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xarch_device", "-O0",
              "-I" + INCLUDE, "-I" + CSRC] + san
 
     def one(src):
@@ -111,7 +112,7 @@ def build_host_sanitized(out_dir: str) -> str:
     with cf.ThreadPoolExecutor(min(len(srcs), max(1, min(8, os.cpu_count() or 1)))) as ex:
         objs = list(ex.map(one, srcs))
     lib = os.path.join(out_dir, "libhafgpu_host_asan.so")
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "--offload-host-only", "-shared-libsan"] + san + [
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-shared-libsan"] + san + [
         "-o", lib] + objs + ["-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx",
                              "-Wl,-rpath," + os.path.join(ROCM, "lib")]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -21,7 +21,8 @@ import os, sys
 import numpy as np
 sys.path.insert(0, os.environ["HAF_ROOT"])
 import paper_1805_12498_amd._native as nat
-nat.LIB_PATH = os.environ["HAF_ASAN_LIB"]
+lib = nat.load(os.environ["HAF_ASAN_LIB"])          # the sanitized build, before anything loads the other
+assert lib._name == os.environ["HAF_ASAN_LIB"], lib._name
 import paper_1805_12498_amd as hg
 HafError = nat.HafError
 
@@ -59,7 +60,6 @@ try:
 except HafError:
     pass
 
-lib = hg.load()
 for v in ("1", "64K", "3M", "1G", "", "x", "-5"):
     os.environ["HAF_ARENA_BYTES"] = v
     c = nat.ServerConfig()
