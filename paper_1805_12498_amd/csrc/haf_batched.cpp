@@ -63,14 +63,15 @@ static int check_config(const haf_batched_config& c) {
 }
 
 // Layout that serves subsets of s rows under table t: the single-matrix layout
-// (t = 0) or the one with the smallest multiple of 8 rows at or above s (t = 1).
-// Both have the same P, Q and polynomial split for every s, so results agree
-// bit for bit; the coarse table has fewer stages and more padding.
+// (t = 0) or the first layout of the same family (P, Q and polynomial split)
+// with a multiple of 8 rows at or above s, if there is one (t = 1).  Layouts of
+// one family give bitwise the same results; the coarse table has fewer stages
+// and more padding.
 static int stage_layout(int table, int s) {
     const int fine = reg_layout_index(s);
     if (table == 0 || fine < 0) return fine;
     for (int l = fine; l < reg_layout_count(); ++l)
-        if (reg_layout_sm(l) % 8 == 0) return l;
+        if (reg_layout_family(l) == reg_layout_family(fine) && reg_layout_sm(l) % 8 == 0) return l;
     return fine;
 }
 

@@ -61,8 +61,9 @@ struct RegShape {
     // the packed table (+ slack) overwrites both
     static constexpr int AREA = RED + VEC > GN + SLACK ? RED + VEC : GN + SLACK;
     static constexpr int PER = AREA + SM;                  // + subdiagonal
+    static constexpr int NI = (SM + L - 1) / L;            // vector indices per lane: lam, lam + L
     static_assert(L * W == 64, "group size must divide 64");
-    static_assert(SM <= L, "the polynomial stage needs one lane per degree");
+    static_assert(NI <= 2, "at most two vector indices per lane");
     static_assert((P & (P - 1)) == 0 && (Q & (Q - 1)) == 0 && P <= SM, "tree sums over P and Q; P norms fit the spare");
 };
 
@@ -245,7 +246,12 @@ __device__ __forceinline__ void write_coefs_range(double2* __restrict__ coef, in
 // CP selects how the polynomial stage uses the wave: 0 = every group on its own
 // matrix, 1 = the whole wave on one matrix at a time with the rows split over the
 // W lane groups, 2 = one matrix per wave, degrees in two passes (below 32 with the
-// rows split over the two lane halves, then the rest).
+// rows split over the two lane halves, then the rest), 3 = the groups in pairs,
+// each 32-lane half of the wave over the degrees of one matrix (for groups of
+// fewer lanes than the matrix has rows).
+//
+// Vector stages give lane lam of a group the indices lam and, when the matrix
+// has more rows than the group has lanes, lam + L.
 template <int P, int Q, int R, int C, int CP, bool LOOPS>
 __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const double2* __restrict__ A, int lda,
                                               int N, int m, uint64_t rank0, int count,
@@ -253,7 +259,8 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                                               double diag_scale, double2* __restrict__ coef, int64_t cstride,
                                               int grp0, int span, int tid) {
     using S = RegShape<P, Q, R, C>;
-    constexpr int L = S::L, W = S::W, SM = S::SM;
+    constexpr int L = S::L, W = S::W, SM = S::SM, NI = S::NI;
+    static_assert(CP == 3 ? (W % 2 == 0 && SM <= 32) : SM <= L, "the polynomial stage needs one lane per degree");
 
     const int g = tid / L;                    // group (matrix) in the wave
     const int lam = tid % L;                  // lane in the group
@@ -281,16 +288,23 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
 
         // ---- loop moments l_k = d^T B^(k-1) X d  (lane lam owns index lam of d)
         if (LOOPS) {
-            const int vl = lam < s ? subset_vertex(mask, lam) : 0;
-            const double2 dl = lam < s ? cscale(A[(int64_t)vl * lda + vl], diag_scale) : cz();
-            const double2 dp = lam < s ? cscale(A[(int64_t)(vl ^ 1) * lda + (vl ^ 1)], diag_scale) : cz();
+            double2 dl[NI], dp[NI];
+#pragma unroll
+            for (int z = 0; z < NI; ++z) {
+                const int i = lam + z * L;
+                const int vl = i < s ? subset_vertex(mask, i) : 0;
+                dl[z] = i < s ? cscale(A[(int64_t)vl * lda + vl], diag_scale) : cz();
+                dp[z] = i < s ? cscale(A[(int64_t)(vl ^ 1) * lda + (vl ^ 1)], diag_scale) : cz();
+            }
             double2 yc[C];                     // y at own columns; y_0 = X d, (X d)_c = d_{c^1}
 #pragma unroll
             for (int u = 0; u < C; ++u) {
                 const int vc = (b + Q * u < s) ? subset_vertex(mask, b + Q * u) ^ 1 : 0;
                 yc[u] = (b + Q * u < s) ? cscale(A[(int64_t)vc * lda + vc], diag_scale) : cz();
             }
-            double2 prod = cmul(dl, dp);
+            double2 prod = cmul(dl[0], dp[0]);
+#pragma unroll
+            for (int z = 1; z < NI; ++z) prod = cadd(prod, cmul(dl[z], dp[z]));
             double lx = group_sum<L>(prod.x), ly = group_sum<L>(prod.y);
             if (valid && lam == 0) coef[(int64_t)N * cstride + sub] = make_double2(lx, ly);
             for (int k = 2; k <= N; ++k) {
@@ -304,14 +318,22 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                 }
                 __builtin_amdgcn_s_setprio(2);    // sums, moment and broadcast: the serial part
                 __syncthreads();
-                double2 yr = cz();            // (B y)_lam
-                if (lam < s) yr = tree_sum<Q, S::YB>(ypart + lam);
-                prod = cmul(dl, yr);
+                double2 yr[NI];               // (B y) at the lane's indices
+#pragma unroll
+                for (int z = 0; z < NI; ++z) {
+                    const int i = lam + z * L;
+                    yr[z] = i < s ? tree_sum<Q, S::YB>(ypart + i) : cz();
+                }
+                prod = cmul(dl[0], yr[0]);
+#pragma unroll
+                for (int z = 1; z < NI; ++z) prod = cadd(prod, cmul(dl[z], yr[z]));
                 lx = group_sum<L>(prod.x);
                 ly = group_sum<L>(prod.y);
                 if (valid && lam == 0) coef[(int64_t)(N + k - 1) * cstride + sub] = make_double2(lx, ly);
                 if (k == N) break;
-                if (lam < SM) yb[lam] = yr;
+#pragma unroll
+                for (int z = 0; z < NI; ++z)
+                    if (lam + z * L < SM) yb[lam + z * L] = yr[z];
                 __syncthreads();
 #pragma unroll
                 for (int u = 0; u < C; ++u) yc[u] = (b + Q * u < s) ? yb[b + Q * u] : cz();
@@ -332,7 +354,12 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
         for (int j = 0; j + 2 < s; ++j) {
             __builtin_amdgcn_s_setprio(2);    // the reflector's serial part issues first
             __syncthreads();                  // column j is in colb, its row-group norms in nrmp
-            const double2 x = (lam > j && lam < s) ? colb[lam] : cz();
+            double2 x[NI];
+#pragma unroll
+            for (int z = 0; z < NI; ++z) {
+                const int i = lam + z * L;
+                x[z] = (i > j && i < s) ? colb[i] : cz();
+            }
             const double2 alpha = colb[j + 1];
             // squared norm below the subdiagonal; rows past s are zero in the tile
             const double sig = tree_sum_d<P>(nrmp);
@@ -341,7 +368,9 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             // below 2^-660 is rounding noise of an already reduced (rank-deficient) part:
             // leave it (the bound also keeps 1 / (beta |alpha - beta|^2) below 2^990)
             const bool skip = tot < 0x1p-660 || (sig == 0.0 && alpha.y == 0.0);
-            double2 tau = cz(), v = cz();
+            double2 tau = cz(), v[NI];
+#pragma unroll
+            for (int z = 0; z < NI; ++z) v[z] = cz();
             double bet = alpha.x;
             if (!skip) {
                 // reflector P = I - tau v v^H with v unnormalised: v_{j+1} = d = alpha - beta,
@@ -352,9 +381,15 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                 const double2 d = make_double2(alpha.x - bet, alpha.y);
                 const double rb = -rcp_normal(bet * fma(d.x, d.x, d.y * d.y));
                 tau = cscale(d, rb);
-                v = lam == j + 1 ? d : (lam > j + 1 ? x : cz());
+#pragma unroll
+                for (int z = 0; z < NI; ++z) {
+                    const int i = lam + z * L;
+                    v[z] = i == j + 1 ? d : (i > j + 1 ? x[z] : cz());
+                }
             }
-            if (lam < SM) vv[lam] = v;
+#pragma unroll
+            for (int z = 0; z < NI; ++z)
+                if (lam + z * L < SM) vv[lam + z * L] = v[z];
             if (lam == 0) beta[j + 1] = skip ? alpha : make_double2(bet, 0.0);
             __syncthreads();
             double2 vr[R];
@@ -383,17 +418,27 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             for (int t = 0; t < R; ++t) ypart[a + P * t + S::YB * b] = yp[t];
             __builtin_amdgcn_s_setprio(2);
             __syncthreads();
-            // lane lam owns column lam (w) and row lam (y)
-            double2 w = cz(), y = cz();
-            if (lam > j && lam < s) w = tree_sum<P, S::WA>(wpart + lam);
-            if (lam < s) y = tree_sum<Q, S::YB>(ypart + lam);
-            const double2 wv = cmul(w, v);
+            // lane lam owns column and row lam (and lam + L): their w and y sums
+            double2 w[NI], y[NI];
+#pragma unroll
+            for (int z = 0; z < NI; ++z) {
+                const int i = lam + z * L;
+                w[z] = (i > j && i < s) ? tree_sum<P, S::WA>(wpart + i) : cz();
+                y[z] = i < s ? tree_sum<Q, S::YB>(ypart + i) : cz();
+            }
+            double2 wv = cmul(w[0], v[0]);
+#pragma unroll
+            for (int z = 1; z < NI; ++z) wv = cadd(wv, cmul(w[z], v[z]));
             const double2 gam = make_double2(group_sum<L>(wv.x), group_sum<L>(wv.y));
-            double2 y1 = y;
-            cfms(y1, cmul(cconj(tau), gam), v);
-            if (lam < SM) {
-                wb[lam] = cmul(cconj(tau), w);
-                yb[lam] = cmul(tau, y1);
+#pragma unroll
+            for (int z = 0; z < NI; ++z) {
+                const int i = lam + z * L;
+                double2 y1 = y[z];
+                cfms(y1, cmul(cconj(tau), gam), v[z]);
+                if (i < SM) {
+                    wb[i] = cmul(cconj(tau), w[z]);
+                    yb[i] = cmul(tau, y1);
+                }
             }
             __syncthreads();
             double2 yr[R];
@@ -447,18 +492,24 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             }
         __syncthreads();
         for (int z = lam; z < S::SLACK; z += L) red[s * (s + 1) / 2 + z] = cz();   // slack after the table
-        // g_{r,c+1} = h_{r,c} prod_{k=r+1}^{c} h_{k,k-1}: lane r walks its row; the
-        // trip count is the same for every lane (lanes join at c = r), so the loop
-        // unrolls and the reads of the next subdiagonal entries are issued early
+        // g_{r,c+1} = h_{r,c} prod_{k=r+1}^{c} h_{k,k-1}: lane r walks its row (and row
+        // r + L); the trip count is the same for every lane (lanes join at c = r), so
+        // the loop unrolls and the reads of the next subdiagonal entries are issued early
         {
-            double2 pi = cone();
+            double2 pi[NI];
+#pragma unroll
+            for (int z = 0; z < NI; ++z) pi[z] = cone();
 #pragma unroll 4
             for (int c = 0; c < s; ++c) {
                 const double2 bc = beta[c + 1 < s ? c + 1 : 0];
-                if (c >= lam && lam < s) {
-                    const int idx = c * (c + 1) / 2 + lam;
-                    red[idx] = cmul(red[idx], pi);
-                    pi = cmul(pi, bc);
+#pragma unroll
+                for (int z = 0; z < NI; ++z) {
+                    const int r = lam + z * L;
+                    if (c >= r && r < s) {
+                        const int idx = c * (c + 1) / 2 + r;
+                        red[idx] = cmul(red[idx], pi[z]);
+                        pi[z] = cmul(pi[z], bc);
+                    }
                 }
             }
         }
@@ -490,6 +541,23 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                     default: break;
                 }
                 if (g == 0) write_coefs(coef, cstride, subg < count, subg, s, N, lam, L, cs);
+            }
+        } else if (CP == 3) {                 // groups in pairs: each 32-lane half over one matrix's degrees
+            const int half = tid >> 5, dd = tid & 31;
+#pragma unroll 1
+            for (int pr = 0; pr < W / 2; ++pr) {
+                const int gg = 2 * pr + half;
+                const int subg = (grp0 + gg) * span + q;
+                const double2* gt = lds + gg * S::PER;
+                double2 cs = cz();
+                switch (s) {
+#define HAF_CP_CASE(SS) case SS: if (SS <= SM && SS + 8 > SM) \
+                    cs = charpoly_lanes<(SS <= SM ? SS : 2), 1, 0>(gt, dd, 0, 0, nullptr, nullptr, 0); break;
+                    HAF_CP_CASES
+#undef HAF_CP_CASE
+                    default: break;
+                }
+                write_coefs(coef, cstride, subg < count, subg, s, N, dd, 32, cs);
             }
         } else {                              // W == 1: degree passes d < 32, then d >= 32
             const int hh = lam / 32, dd = lam % 32;
@@ -531,7 +599,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
 // subset (padded rows and columns only add exact zeros; every sum runs over the
 // same P or Q partials in the same order).
 #define HAF_REG_TABLE(X) X(4, 4, 2, 2, 0, 0, 8) X(4, 4, 3, 3, 0, 8, 12) X(4, 4, 4, 4, 0, 12, 16)       \
-                          X(8, 4, 3, 5, 0, 16, 20) \
+                          X(4, 4, 5, 5, 3, 16, 20) \
                           X(8, 4, 3, 6, 0, 20, 24) X(8, 4, 4, 7, 1, 24, 28) X(8, 4, 4, 8, 1, 28, 32)      \
                           X(8, 8, 5, 5, 2, 32, 40) X(8, 8, 6, 6, 2, 40, 48)
 

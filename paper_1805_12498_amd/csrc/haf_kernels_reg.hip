@@ -114,6 +114,15 @@ int reg_layout_groups(int layout) {
     return 0;
 }
 
+int reg_layout_family(int layout) {
+    int i = 0;
+#define HAF_FAMILY_OF(P, Q, R, C, CP, LO, HI) \
+    if (i++ == layout) return (P << 16) | (Q << 8) | CP;
+    HAF_REG_TABLE(HAF_FAMILY_OF)
+#undef HAF_FAMILY_OF
+    return -1;
+}
+
 int group_coef_blocks(int layout, int count, int span) {
     const int w = reg_layout_groups(layout) * (span > 0 ? span : 1);
     return w > 0 ? (count + w - 1) / w : 0;

@@ -88,6 +88,7 @@ hipError_t launch_group_prologue(hipStream_t st, const GroupItem* items, int nit
 int reg_layout_count();
 int reg_layout_sm(int layout);           // largest s of the layout
 int reg_layout_groups(int layout);       // matrices per wave
+int reg_layout_family(int layout);       // (P, Q, CP) packed: layouts of one family agree bit for bit
 int group_coef_blocks(int layout, int count, int span);
 hipError_t launch_coef_reg_group(int layout, bool loops, int blocks, hipStream_t st, const GroupItem* items,
                                  const GroupChunk* chunks, int nchunks, double2* coef);
