@@ -12,7 +12,8 @@
 //    the active trailing block of the reduction shrinks);
 //  * the reduction step index j is a runtime loop; tile slots are static and
 //    column slots left of the active block are skipped with uniform branches, so
-//    nothing is indexed dynamically in registers;
+//    nothing is indexed dynamically in registers (small tiles also drop, per phase
+//    of the loop, the left-update terms of row slots above the reflector);
 //  * one reduction step is one pass over the tile: with P = I - tau v v^H,
 //        P^H H P = H - v w'^T - y1 v^H,   w' = conj(tau) (v^H H)^T,
 //        y1 = tau (H v - conj(tau) gamma v),  gamma = v^H H v,
@@ -37,10 +38,23 @@
 // the multi-chunk kernel and the shared batched / serving stage kernel run exactly
 // the same arithmetic.
 #pragma once
+#include <type_traits>
+#include <utility>
+
 #include "haf_common.hpp"
 
 namespace hafgpu {
 
+
+// f(std::integral_constant<int, 0>{}), ..., f(std::integral_constant<int, N - 1>{})
+template <int... I, class F>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, F&& f) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(std::make_integer_sequence<int, N>{}, f);
+}
 
 template <int P, int Q, int R, int C>
 struct RegShape {
@@ -351,7 +365,10 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
             }
             nrmp[a] = part;
         }
-        for (int j = 0; j + 2 < s; ++j) {
+        // one Householder step; row slots below TLO hold only rows <= j, where v = 0,
+        // so the left-update terms of those slots are left out at compile time
+        auto hh_step = [&](const int j, auto tlo_c) {
+            constexpr int TLO = decltype(tlo_c)::value;
             __builtin_amdgcn_s_setprio(2);    // the reflector's serial part issues first
             __syncthreads();                  // column j is in colb, its row-group norms in nrmp
             double2 x[NI];
@@ -409,7 +426,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                     double2 wp = cz();
 #pragma unroll
                     for (int t = 0; t < R; ++t) {
-                        cfma_cj(wp, vr[t], h[t][u]);
+                        if (t >= TLO) cfma_cj(wp, vr[t], h[t][u]);
                         cfma(yp[t], h[t][u], vcu);
                     }
                     wpart[b + Q * u + S::WA * a] = wp;
@@ -452,7 +469,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                     const double2 vcu = (b + Q * u < SM) ? vv[b + Q * u] : cz();
 #pragma unroll
                     for (int t = 0; t < R; ++t) {
-                        cfms(h[t][u], vr[t], wu);
+                        if (t >= TLO) cfms(h[t][u], vr[t], wu);
                         cfms_cj(h[t][u], yr[t], vcu);
                     }
                 }
@@ -473,6 +490,19 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                         nrmp[a] = part;
                     }
             }
+        };
+        if constexpr (R * C <= 16) {
+            // small tiles: one copy of the step per phase, phase PH running the steps with
+            // (j + 1) / P == PH (row slots below PH hold rows <= j); larger tiles keep one copy,
+            // since the copies cost them registers and time more than the skipped terms save
+            static_for<R>([&](auto ph) {
+                constexpr int PH = decltype(ph)::value;
+                const int jlo = PH == 0 ? 0 : PH * P - 1;
+                const int jhi = PH == R - 1 ? s - 2 : min(s - 2, (PH + 1) * P - 1);
+                for (int j = jlo; j < jhi; ++j) hh_step(j, std::integral_constant<int, PH>{});
+            });
+        } else {
+            for (int j = 0; j + 2 < s; ++j) hh_step(j, std::integral_constant<int, 0>{});
         }
         __builtin_amdgcn_s_setprio(2);        // table, scaling walk: LDS latency chains
         // ---- the last subdiagonal entry (no reflector acts on it)
