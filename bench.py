@@ -43,9 +43,9 @@ PEAK_FP64_TFLOPS = 78.6          # MI355X vector FP64: 256 CU x 128 flop/clk x 2
 #    (profiles/coef_kernel_n56_haf_sq_counters.md).
 COUNTER_SOURCES = ("paper_1805_12498_amd/csrc/haf_coef_reg.hpp", "paper_1805_12498_amd/csrc/haf_kernels_reg.hip",
                    "paper_1805_12498_amd/csrc/haf_common.hpp")
-COUNTER_SHA256 = "39e517d0b864051aba7a959c9244abc4822a57a70fc2535f0df3df5768eb820b"
-TRAFFIC_N56_HAF_BYTES_PER_LAUNCH = 8.846e8
-COUNTER_N56_HAF_FP64_FLOPS_PER_STEP = 2.126e14
+COUNTER_SHA256 = "f8b13f715d870bcb608033f85d691c5afd38a80826df9c8206c79ba25c7ac906"
+TRAFFIC_N56_HAF_BYTES_PER_LAUNCH = 8.837e8
+COUNTER_N56_HAF_FP64_FLOPS_PER_STEP = 2.125e14
 
 
 def counters_valid(n, kind):
