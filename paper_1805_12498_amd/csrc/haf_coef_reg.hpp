@@ -12,8 +12,8 @@
 //    the active trailing block of the reduction shrinks);
 //  * the reduction step index j is a runtime loop; tile slots are static and
 //    column slots left of the active block are skipped with uniform branches, so
-//    nothing is indexed dynamically in registers (small tiles also drop, per phase
-//    of the loop, the left-update terms of row slots above the reflector);
+//    nothing is indexed dynamically in registers (some layouts also drop, per
+//    phase of the loop, the left-update terms of row slots above the reflector);
 //  * one reduction step is one pass over the tile: with P = I - tau v v^H,
 //        P^H H P = H - v w'^T - y1 v^H,   w' = conj(tau) (v^H H)^T,
 //        y1 = tau (H v - conj(tau) gamma v),  gamma = v^H H v,
@@ -491,10 +491,12 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                     }
             }
         };
-        if constexpr (R * C <= 16) {
-            // small tiles: one copy of the step per phase, phase PH running the steps with
-            // (j + 1) / P == PH (row slots below PH hold rows <= j); larger tiles keep one copy,
-            // since the copies cost them registers and time more than the skipped terms save
+        // One copy of the step per phase, phase PH running the steps with (j + 1) / P == PH
+        // (row slots below PH hold rows <= j), where the copies do not cost more registers and
+        // time than the skipped terms save: the tiles up to 4 x 4, and the 3 x 6 and 5 x 5
+        // tiles without the loop moments (which leave them the registers).  Chosen by measurement.
+        constexpr bool PHASED = R * C <= 16 || (!LOOPS && ((R == 3 && C == 6) || (P == 8 && Q == 8 && R == 5 && C == 5)));
+        if constexpr (PHASED) {
             static_for<R>([&](auto ph) {
                 constexpr int PH = decltype(ph)::value;
                 const int jlo = PH == 0 ? 0 : PH * P - 1;
