@@ -5,8 +5,15 @@
 
 namespace hafgpu {
 
+// Lower bound on waves per SIMD that the compiler must keep room for: two for the
+// tiles of 36 entries and more; three for the 3 x 3 tile, which the compiler then
+// fits in 168 registers with a few spilled bytes (the batched call 1.4-2% faster,
+// bitwise-equal results; the 2 x 2 tile at four waves and the 4 x 4 tile at three
+// were no faster); no bound otherwise.
+#define HAF_REG_WAVES(R, C) ((R) * (C) >= 36 ? 2 : ((R) * (C) == 9 ? 3 : 1))
+
 template <int P, int Q, int R, int C, int CP, bool LOOPS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 ? 2 : 1))) void k_coef_reg(const double2* __restrict__ A, int lda, int N, int m,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HAF_REG_WAVES(R, C)))) void k_coef_reg(const double2* __restrict__ A, int lda, int N, int m,
                                                  uint64_t rank0, int count, const uint32_t* __restrict__ masks,
                                                  const int* __restrict__ d_exp, double2* __restrict__ coef,
                                                  int64_t cstride) {
@@ -31,7 +38,7 @@ int reg_max_s() { return 48; }
 // Several chunks of one matrix: the workgroup finds its chunk in the table (a
 // short uniform scan), then runs the same per-subset body as k_coef_reg.
 template <int P, int Q, int R, int C, int CP, bool LOOPS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 ? 2 : 1))) void k_coef_reg_multi(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HAF_REG_WAVES(R, C)))) void k_coef_reg_multi(
     const double2* __restrict__ A, int lda, int N, const int* __restrict__ d_exp, double2* __restrict__ coef,
     MultiChunks mc) {
     using S = RegShape<P, Q, R, C>;
@@ -58,7 +65,7 @@ HAF_REG_TABLE(HAF_INST_REG_MULTI)
 // the launch's chunk table (uniform), then runs the per-subset body for the
 // chunk's matrix (its own N, exponent and subset ranks).
 template <int P, int Q, int R, int C, int CP, bool LOOPS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R * C >= 36 ? 2 : 1))) void k_coef_reg_group(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HAF_REG_WAVES(R, C)))) void k_coef_reg_group(
     const GroupItem* __restrict__ items, const GroupChunk* __restrict__ chunks, int nchunks,
     double2* __restrict__ coef) {
     using S = RegShape<P, Q, R, C>;
