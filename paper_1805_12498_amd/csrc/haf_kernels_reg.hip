@@ -1,5 +1,7 @@
 // One-size-class launch of the register-tiled per-subset stage: the grid's
 // groups split the chunk's subsets into equal contiguous runs.
+#include <algorithm>
+
 #include "haf_coef_reg.hpp"
 #include "haf_launch.hpp"
 
@@ -188,19 +190,39 @@ hipError_t launch_coef_reg_multi(int s_max, bool loops, int grid_waves, hipStrea
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_coef_reg(int s, bool loops, int grid_waves, hipStream_t st, const double2* A, int lda, int N,
+// Workgroups of one launch: whole rounds of the kernel's resident one-wave workgroups
+// (a partial last round leaves SIMDs idle while it drains), as many rounds as keep at
+// least 32 subsets per lane group, up to eight (shorter workgroups also end more evenly).
+template <int P, int Q, int R, int C, int CP, bool LOOPS>
+static int coef_reg_grid(int cus, int count) {
+    constexpr int W = RegShape<P, Q, R, C>::W;
+    static const int per_cu = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_coef_reg<P, Q, R, C, CP, LOOPS>, 64, 0) != hipSuccess ||
+            b < 1)
+            b = 8;
+        return b;
+    }();
+    const int64_t slots = (int64_t)per_cu * cus;
+    int64_t rounds = 1;
+    while (rounds < 8 && slots * W * 32 * (rounds * 2) <= (int64_t)count) rounds *= 2;
+    return (int)std::min<int64_t>(rounds * slots, ((int64_t)count + W - 1) / W);
+}
+
+hipError_t launch_coef_reg(int s, bool loops, int cus, hipStream_t st, const double2* A, int lda, int N,
                            int m, uint64_t rank0, int count, const uint32_t* masks, const int* d_exp,
                            double2* coef, int64_t cstride) {
     if (count <= 0) return hipSuccess;
 #define HAF_TRY_REG(P, Q, R, C, CP, LO, HI)                                                                   \
     if (s > LO && s <= HI) {                                                                                  \
-        constexpr int W = RegShape<P, Q, R, C>::W;                                                            \
-        int grid = (count + W - 1) / W;                                                                       \
-        if (grid > grid_waves) grid = grid_waves;                                                             \
-        if (loops) hipLaunchKernelGGL((k_coef_reg<P, Q, R, C, CP, true>), dim3(grid), dim3(64), 0, st, A,     \
-                                      lda, N, m, rank0, count, masks, d_exp, coef, cstride);                  \
-        else hipLaunchKernelGGL((k_coef_reg<P, Q, R, C, CP, false>), dim3(grid), dim3(64), 0, st, A, lda,     \
-                                N, m, rank0, count, masks, d_exp, coef, cstride);                             \
+        if (loops)                                                                                            \
+            hipLaunchKernelGGL((k_coef_reg<P, Q, R, C, CP, true>),                                            \
+                               dim3(coef_reg_grid<P, Q, R, C, CP, true>(cus, count)), dim3(64), 0, st, A, lda, \
+                               N, m, rank0, count, masks, d_exp, coef, cstride);                              \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_coef_reg<P, Q, R, C, CP, false>),                                           \
+                               dim3(coef_reg_grid<P, Q, R, C, CP, false>(cus, count)), dim3(64), 0, st, A,    \
+                               lda, N, m, rank0, count, masks, d_exp, coef, cstride);                         \
         return hipGetLastError();                                                                             \
     }
     HAF_REG_TABLE(HAF_TRY_REG)

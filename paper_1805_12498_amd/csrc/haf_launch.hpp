@@ -15,8 +15,9 @@ hipError_t launch_coef_lds(int smax, bool loops, int grid, hipStream_t st, const
                            int64_t cstride);
 
 // Register-tiled coefficient kernel for subsets of s <= reg_max_s() rows (same
-// outputs).  grid_waves bounds the number of one-wave workgroups.
-hipError_t launch_coef_reg(int s, bool loops, int grid_waves, hipStream_t st, const double2* A, int lda, int N,
+// outputs).  cus is the device's compute-unit count; the launch sizes its grid
+// of one-wave workgroups from it and the kernel's occupancy.
+hipError_t launch_coef_reg(int s, bool loops, int cus, hipStream_t st, const double2* A, int lda, int N,
                            int m, uint64_t rank0, int count, const uint32_t* masks, const int* d_exp,
                            double2* coef, int64_t cstride);
 int reg_max_s();

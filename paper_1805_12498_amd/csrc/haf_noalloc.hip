@@ -59,7 +59,7 @@ static int noalloc_chunk(int dev, const double2* dA, int lda, int N, int m, uint
     const int s = 2 * m;
     hipError_t e;
     if (kernel_path() != 1 && s <= reg_max_s())
-        e = launch_coef_reg(s, loops, device_cus(dev) * 16, st, dA, lda, N, m, rank0, count, nullptr, d_exp, coef,
+        e = launch_coef_reg(s, loops, device_cus(dev), st, dA, lda, N, m, rank0, count, nullptr, d_exp, coef,
                             count);
     else
         e = launch_coef_lds(s, loops, coef_grid(dev, count), st, dA, lda, N, m, rank0, count, nullptr, d_exp, coef,

@@ -292,7 +292,7 @@ int launch_coef_chunk(int dev, const double2* dA, int lda, int N, int m, uint64_
     const int pidx = prof_begin(st, 0, (double)count * coef_model_flops(s, N, loops), count);
     hipError_t e;
     if (g_kernel_path != 1 && s <= reg_max_s())
-        e = launch_coef_reg(s, loops, device_cus(dev) * 16, st, dA, lda, N, m, rank0, count, masks, d_exp, coef,
+        e = launch_coef_reg(s, loops, device_cus(dev), st, dA, lda, N, m, rank0, count, masks, d_exp, coef,
                             cstride);
     else
         e = launch_coef_lds(s, loops, coef_grid(dev, count), st, dA, lda, N, m, rank0, count, masks, d_exp, coef,
