@@ -241,29 +241,38 @@ __device__ __forceinline__ double2 charpoly_lanes(const double2* __restrict__ gt
     HAF_CP_CASE(26) HAF_CP_CASE(28) HAF_CP_CASE(30) HAF_CP_CASE(32) HAF_CP_CASE(34) HAF_CP_CASE(36)         \
     HAF_CP_CASE(38) HAF_CP_CASE(40) HAF_CP_CASE(42) HAF_CP_CASE(44) HAF_CP_CASE(46) HAF_CP_CASE(48)
 
-// Coefficient stores are nontemporal: each lane writes 16 B of a different line and a
-// line fills over several subsets of its group; as streaming stores they leave the
-// kernel with about a third less HBM write traffic at the same speed.
+// Each lane writes 16 B of a different line and a line fills over several subsets of
+// its group.  With NTS the stores are nontemporal: launches over one large chunk then
+// leave about a third less HBM write traffic at the same speed.  The batched and
+// server stages, whose series launch reads the coefficients back at once, keep
+// ordinary stores (nontemporal ones made the batched call 0.4% slower).
+template <bool NTS>
 __device__ __forceinline__ void store_coef(double2* p, double2 v) {
-    typedef double v2d __attribute__((ext_vector_type(2)));
-    const v2d x = { v.x, v.y };
-    __builtin_nontemporal_store(x, reinterpret_cast<v2d*>(p));
+    if constexpr (NTS) {
+        typedef double v2d __attribute__((ext_vector_type(2)));
+        const v2d x = { v.x, v.y };
+        __builtin_nontemporal_store(x, reinterpret_cast<v2d*>(p));
+    } else {
+        *p = v;
+    }
 }
 
 // a_k = c_s[s-k], the lambda^k coefficient of det(I - lambda B), from lane d, plus
 // zeros for s < k <= N
+template <bool NTS>
 __device__ __forceinline__ void write_coefs(double2* __restrict__ coef, int64_t cstride, bool valid, int sub, int s,
                                             int N, int d, int L, double2 cs) {
     if (!valid) return;
     const int k = s - d;
-    if (d < s && k <= N) store_coef(&coef[(int64_t)(k - 1) * cstride + sub], cs);
-    for (int kk = s + 1 + d; kk <= N; kk += L) store_coef(&coef[(int64_t)(kk - 1) * cstride + sub], cz());
+    if (d < s && k <= N) store_coef<NTS>(&coef[(int64_t)(k - 1) * cstride + sub], cs);
+    for (int kk = s + 1 + d; kk <= N; kk += L) store_coef<NTS>(&coef[(int64_t)(kk - 1) * cstride + sub], cz());
 }
+template <bool NTS>
 __device__ __forceinline__ void write_coefs_range(double2* __restrict__ coef, int64_t cstride, bool valid, int sub,
                                                   int s, int N, int d, int dlo, int dhi, double2 cs) {
     if (!valid || d < dlo || d >= dhi || d >= s) return;
     const int k = s - d;
-    if (k <= N) store_coef(&coef[(int64_t)(k - 1) * cstride + sub], cs);
+    if (k <= N) store_coef<NTS>(&coef[(int64_t)(k - 1) * cstride + sub], cs);
 }
 
 // CP selects how the polynomial stage uses the wave: 0 = every group on its own
@@ -275,7 +284,7 @@ __device__ __forceinline__ void write_coefs_range(double2* __restrict__ coef, in
 //
 // Vector stages give lane lam of a group the indices lam and, when the matrix
 // has more rows than the group has lanes, lam + L.
-template <int P, int Q, int R, int C, int CP, bool LOOPS>
+template <int P, int Q, int R, int C, int CP, bool LOOPS, bool NTS = true>
 __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const double2* __restrict__ A, int lda,
                                               int N, int m, uint64_t rank0, int count,
                                               const uint32_t* __restrict__ masks, double off_scale,
@@ -329,7 +338,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
 #pragma unroll
             for (int z = 1; z < NI; ++z) prod = cadd(prod, cmul(dl[z], dp[z]));
             double lx = group_sum<L>(prod.x), ly = group_sum<L>(prod.y);
-            if (valid && lam == 0) store_coef(&coef[(int64_t)N * cstride + sub], make_double2(lx, ly));
+            if (valid && lam == 0) store_coef<NTS>(&coef[(int64_t)N * cstride + sub], make_double2(lx, ly));
             for (int k = 2; k <= N; ++k) {
                 __builtin_amdgcn_s_setprio(0);
 #pragma unroll
@@ -352,7 +361,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
                 for (int z = 1; z < NI; ++z) prod = cadd(prod, cmul(dl[z], yr[z]));
                 lx = group_sum<L>(prod.x);
                 ly = group_sum<L>(prod.y);
-                if (valid && lam == 0) store_coef(&coef[(int64_t)(N + k - 1) * cstride + sub], make_double2(lx, ly));
+                if (valid && lam == 0) store_coef<NTS>(&coef[(int64_t)(N + k - 1) * cstride + sub], make_double2(lx, ly));
                 if (k == N) break;
 #pragma unroll
                 for (int z = 0; z < NI; ++z)
@@ -567,7 +576,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
 #undef HAF_CP_CASE
                 default: break;
             }
-            write_coefs(coef, cstride, valid, sub, s, N, lam, L, cs);
+            write_coefs<NTS>(coef, cstride, valid, sub, s, N, lam, L, cs);
         } else if (CP == 1) {                 // whole wave per matrix, rows split over groups
 #pragma unroll 1
             for (int gg = 0; gg < W; ++gg) {
@@ -581,7 +590,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
 #undef HAF_CP_CASE
                     default: break;
                 }
-                if (g == 0) write_coefs(coef, cstride, subg < count, subg, s, N, lam, L, cs);
+                if (g == 0) write_coefs<NTS>(coef, cstride, subg < count, subg, s, N, lam, L, cs);
             }
         } else if (CP == 3) {                 // groups in pairs: each 32-lane half over one matrix's degrees
             const int half = tid >> 5, dd = tid & 31;
@@ -598,7 +607,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
 #undef HAF_CP_CASE
                     default: break;
                 }
-                write_coefs(coef, cstride, subg < count, subg, s, N, dd, 32, cs);
+                write_coefs<NTS>(coef, cstride, subg < count, subg, s, N, dd, 32, cs);
             }
         } else {                              // W == 1: degree passes d < 32, then d >= 32
             const int hh = lam / 32, dd = lam % 32;
@@ -611,7 +620,7 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
 #undef HAF_CP_CASE
                 default: break;
             }
-            if (hh == 0) write_coefs_range(coef, cstride, valid, sub, s, N, dd, 0, 32, cs);
+            if (hh == 0) write_coefs_range<NTS>(coef, cstride, valid, sub, s, N, dd, 0, 32, cs);
             if (s > 32) {
                 __syncthreads();              // bnd is complete
                 double2 cs2 = cz();
@@ -622,10 +631,10 @@ __device__ __forceinline__ void coef_reg_span(double2* __restrict__ lds, const d
 #undef HAF_CP_CASE
                     default: break;
                 }
-                if (hh == 0) write_coefs_range(coef, cstride, valid, sub, s, N, dd + 32, 32, s, cs2);
+                if (hh == 0) write_coefs_range<NTS>(coef, cstride, valid, sub, s, N, dd + 32, 32, s, cs2);
             }
             if (hh == 0 && valid)
-                for (int kk = s + 1 + dd; kk <= N; kk += 32) store_coef(&coef[(int64_t)(kk - 1) * cstride + sub], cz());
+                for (int kk = s + 1 + dd; kk <= N; kk += 32) store_coef<NTS>(&coef[(int64_t)(kk - 1) * cstride + sub], cz());
         }
         __syncthreads();                      // LDS is reused by the next subset
     }

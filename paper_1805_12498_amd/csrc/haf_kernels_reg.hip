@@ -85,9 +85,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(HAF_REG_WAVE
     const int span = (ch.count + groups - 1) / groups;
     const GroupItem it = items[ch.item];
     const int e = *it.exp;
-    coef_reg_span<P, Q, R, C, CP, LOOPS>(lds, it.A, it.lda, ch.N, ch.m, ch.rank0, ch.count, nullptr,
-                                         ldexp(1.0, -2 * e), ldexp(1.0, -e), coef + ch.coff, ch.count,
-                                         (blk - ch.gstart) * S::W, span, threadIdx.x);
+    coef_reg_span<P, Q, R, C, CP, LOOPS, false>(lds, it.A, it.lda, ch.N, ch.m, ch.rank0, ch.count, nullptr,
+                                                ldexp(1.0, -2 * e), ldexp(1.0, -e), coef + ch.coff, ch.count,
+                                                (blk - ch.gstart) * S::W, span, threadIdx.x);
 }
 
 #define HAF_INST_REG_GROUP(P, Q, R, C, CP, LO, HI)                                                          \
