@@ -43,9 +43,9 @@ PEAK_FP64_TFLOPS = 78.6          # MI355X vector FP64: 256 CU x 128 flop/clk x 2
 #    (profiles/coef_kernel_n56_haf_sq_counters.md).
 COUNTER_SOURCES = ("paper_1805_12498_amd/csrc/haf_coef_reg.hpp", "paper_1805_12498_amd/csrc/haf_kernels_reg.hip",
                    "paper_1805_12498_amd/csrc/haf_common.hpp")
-COUNTER_SHA256 = "13f210cad8def3bcc867bf9cdf0cb4040889dfc1aa3ecb51d86ecf63399a9728"
-TRAFFIC_N56_HAF_BYTES_PER_LAUNCH = 8.808e8
-COUNTER_N56_HAF_FP64_FLOPS_PER_STEP = 2.041e14
+COUNTER_SHA256 = "2c9c6e3752ebb2e5c6ff32d7ff4e4ffa1c31fa83f874e77b379bb291b80ed2d4"
+TRAFFIC_N56_HAF_BYTES_PER_LAUNCH = 9.251e8
+COUNTER_N56_HAF_FP64_FLOPS_PER_STEP = 2.042e14
 
 
 def counters_valid(n, kind):
