@@ -43,7 +43,7 @@ PEAK_FP64_TFLOPS = 78.6          # MI355X vector FP64: 256 CU x 128 flop/clk x 2
 #    (profiles/coef_kernel_n56_haf_sq_counters.md).
 COUNTER_SOURCES = ("paper_1805_12498_amd/csrc/haf_coef_reg.hpp", "paper_1805_12498_amd/csrc/haf_kernels_reg.hip",
                    "paper_1805_12498_amd/csrc/haf_common.hpp")
-COUNTER_SHA256 = "2c9c6e3752ebb2e5c6ff32d7ff4e4ffa1c31fa83f874e77b379bb291b80ed2d4"
+COUNTER_SHA256 = "f9ce639779121b2f3215a01f5ce5d825a3eec39f9b9c92442ec4843992a64f5c"
 TRAFFIC_N56_HAF_BYTES_PER_LAUNCH = 9.251e8
 COUNTER_N56_HAF_FP64_FLOPS_PER_STEP = 2.042e14
 

@@ -198,10 +198,11 @@ static int coef_reg_grid(int cus, int count) {
     constexpr int W = RegShape<P, Q, R, C>::W;
     static const int per_cu = [] {
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_coef_reg<P, Q, R, C, CP, LOOPS>, 64, 0) != hipSuccess ||
-            b < 1)
-            b = 8;
-        return b;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_coef_reg<P, Q, R, C, CP, LOOPS>, 64, 0) != hipSuccess) {
+            (void)hipGetLastError();          // not the launch's error: fall back to two waves per SIMD
+            b = 0;
+        }
+        return b < 1 ? 8 : b;
     }();
     const int64_t slots = (int64_t)per_cu * cus;
     int64_t rounds = 1;
